@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark: rays/s and right-hand-side evaluations/s for the a = 0.99,
+1024x1024 Kerr image pair (inclinations 17 and 60 deg, observer at 1000 M,
+[-12, 12]^2, adaptive DOPRI5 rtol = atol = 1e-8 in FP64, four equatorial
+crossing records per ray).
+
+One step = one pass of the whole path over both images: kh_init_rays (both
+cameras, one launch) + kh_integrate (one persistent launch over 2^21 rays).
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (256 CU x 64 lanes x 2 flop x 2.4 GHz)
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(K, stats, n_rays, method, form):
+    """Operation count of one integrate launch: per DOPRI5 attempt 6 right-hand
+    sides plus the stage combinations and error norm; one extra right-hand side
+    per ray for its first stage."""
+    f = K.kh_flops(method, form)
+    rhs = f["add"] + f["mul"] + f["div"] + f["sqrt"]
+    step = f["step_add"] + f["step_mul"] + f["step_div"] + f["step_sqrt"]
+    attempts = stats["n_acc"] + stats["n_rej"]
+    if method == K.DOPRI5:
+        n_rhs = 6 * attempts + n_rays
+        flops = attempts * (6 * rhs + step) + n_rays * rhs
+    else:
+        n_rhs = 4 * stats["n_acc"] + n_rays
+        flops = stats["n_acc"] * (4 * rhs + step) + n_rays * rhs
+    return flops, n_rhs, rhs, step
+
+
+def run_gpu(args):
+    import torch
+
+    import paper_1706_07062_amd as K
+    from paper_1706_07062_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    ctx = K.Context(0)
+    cams = W.kerr_1024()
+    kc = [K.kh_camera(c.a, c.r_obs, c.incl, c.alpha_min, c.alpha_max, c.beta_min, c.beta_max, c.width, c.height)
+          for c in cams]
+    n = sum(c.n for c in cams)
+    st = K.State(n, k_cross=4)
+    params = K.kh_default_params(k_cross=4)
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        ctx.kh_init_rays(kc, st)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.kh_integrate(params, st)
+        e1.record(stream)
+        return e0, e1
+
+    for i in range(args.warmup):
+        one_step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [one_step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in evs]
+    stats = ctx.kh_stats(st)
+    log(f"timed {args.steps} steps: {wall:.3f} s; integrate kernel {np.mean(kern_ms):.2f} ms avg; stats {stats}")
+    flops, n_rhs, rhs_f, step_f = algorithmic_flops(K, stats, n, K.DOPRI5, K.RHS_FACTORED)
+    ms_step = 1e3 * wall / args.steps
+    kern_s = np.mean(kern_ms) / 1e3
+    tflops = flops / kern_s / 1e12
+    out = dict(
+        metric="rays/s and RHS evals/s at a=0.99 1024^2; surrogate vs integrator at fixed error",
+        value=n * args.steps / wall,
+        unit="rays/s",
+        n_gpus=1,
+        steps=args.steps,
+        warmup=args.warmup,
+        ms_per_step=ms_step,
+        higher_is_better=True,
+        scaling="weak",
+        vs_baseline=None,
+        dtype="f64",
+        data="synthetic",
+        config={"workload": "kerr a=0.99 1024x1024 images at incl 17 and 60 deg, r_obs=1000, alpha,beta in "
+                            "[-12,12], DOPRI5 rtol=atol=1e-8 FP64, 4 equatorial crossings",
+                "rays_per_step": n, "parallelism": "single GPU, persistent kernel"},
+        rhs_evals_per_s=n_rhs * args.steps / wall,
+        rhs_evals_per_step=n_rhs,
+        accepted_steps_per_ray=stats["n_acc"] / n,
+        rejected_steps_per_ray=stats["n_rej"] / n,
+        integrate_kernel_ms=float(np.mean(kern_ms)),
+        roofline=dict(bound="alu", achieved=tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                      frac=tflops / FP64_PEAK_TFLOPS, traffic=None,
+                      flops_per_launch=flops, flop_per_rhs=rhs_f, flop_per_attempt_overhead=step_f),
+    )
+    if not args.no_extras:
+        out["extras"] = extras(args, ctx, K, W, torch)
+    ctx.close()
+    return out, st
+
+
+def extras(args, ctx, K, W, torch):
+    """Secondary figures on the same images: FP32 and mixed precision, and the
+    fixed-step RK4 time per step per ray (the paper's benchmark unit)."""
+    res = {}
+    cams = W.kerr_1024()
+    kc = [K.kh_camera(c.a, c.r_obs, c.incl, c.alpha_min, c.alpha_max, c.beta_min, c.beta_max, c.width, c.height)
+          for c in cams]
+    n = sum(c.n for c in cams)
+    for name, prec, tol in (("fp32", K.P32, 1e-6), ("mixed", K.PMIXED, 1e-8)):
+        st = K.State(n, k_cross=4)
+        p = K.kh_default_params(k_cross=4, precision=prec, rtol=tol, atol=tol)
+        ctx.kh_init_rays(kc, st)
+        ctx.kh_integrate(p, st)
+        torch.cuda.synchronize()
+        ctx.kh_init_rays(kc, st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.kh_integrate(p, st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s = ctx.kh_stats(st)
+        res[name] = dict(rays_per_s=n / dt, kernel_ms=dt * 1e3, rtol=tol,
+                         rhs_evals_per_s=(6 * (s["n_acc"] + s["n_rej"]) + n) / dt)
+        log(f"{name}: {n / dt:.3e} rays/s")
+    # Fixed-step RK4 (h = 0.01 r) on the paper's benchmark geometry: a = 0.999,
+    # image at r = 1024 M, 1024x1024.
+    cam = W.Camera(0.999, 1024.0, 60.0, -12, 12, -12, 12, 1024, 1024)
+    kc1 = [K.kh_camera(cam.a, cam.r_obs, cam.incl, cam.alpha_min, cam.alpha_max, cam.beta_min, cam.beta_max,
+                       cam.width, cam.height)]
+    st = K.State(cam.n)
+    p = K.kh_default_params(method=K.RK4, h_coeff=0.01, r_escape=1024.0)
+    for prec, name in ((K.P64, "rk4_fp64"), (K.P32, "rk4_fp32")):
+        p.precision = prec
+        ctx.kh_init_rays(kc1, st)
+        ctx.kh_integrate(p, st)
+        torch.cuda.synchronize()
+        ctx.kh_init_rays(kc1, st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.kh_integrate(p, st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s = ctx.kh_stats(st)
+        res[name] = dict(ns_per_step_per_ray=dt * 1e9 / s["n_acc"], steps=s["n_acc"], kernel_ms=dt * 1e3,
+                         workload="a=0.999, 1024x1024, r_obs=1024, 60 deg, h=0.01r")
+        log(f"{name}: {res[name]['ns_per_step_per_ray']:.4f} ns per RK4 step per ray")
+    return res
+
+
+def cpu_baseline(args):
+    """The oracle on a bounded sample of the same workload: strided pixels of
+    both images, all host threads."""
+    import oracle as O
+    from paper_1706_07062_amd import workloads as W
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    per_img = args.cpu_sample // 2
+    done, t_total = 0, 0.0
+    for j, cam in enumerate(W.kerr_1024()):
+        pix = W.strided_pixels(cam.n, per_img, offset=j)
+        init = O.camera_rays(cam.a, cam.r_obs, cam.incl, cam.alpha_min, cam.alpha_max, cam.beta_min, cam.beta_max,
+                             cam.width, cam.height, pix=pix)
+        t0 = time.perf_counter()
+        O.integrate(init, O.Params(method=O.DOPRI5, k_cross=4), nthreads=cores)
+        t_total += time.perf_counter() - t0
+        done += len(pix)
+    log(f"cpu oracle: {done} rays in {t_total:.2f} s on {cores} threads")
+    return dict(value=done / t_total, unit="rays/s", cores=cores, kind="oracle",
+                sample=f"{done} strided pixels of the two 1024x1024 a=0.99 images (half each), FP64 DOPRI5 "
+                       f"rtol 1e-8, {t_total:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the integrator shards by ray range with no exchange on the hot "
+              "path, and this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+    out, _ = run_gpu(args)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

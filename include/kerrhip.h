@@ -1,0 +1,194 @@
+/*
+ * kerrhip.h -- C ABI of the MI355X (gfx950) geodesic integrator.
+ *
+ * Batched integration of null and time-like geodesics in Cartesian
+ * Kerr-Schild coordinates (Chan, Medeiros, Ozel & Psaltis, "GRay2", Sec. 2):
+ * one geodesic per GPU lane, state (x^mu, k^mu) with k^mu = dx^mu/dlambda,
+ * right-hand side in the regrouped Kerr-Schild form of eq:opt0 / eq:opti
+ * (metric def:CKS and its analytic derivatives, no Christoffel table), classic
+ * fourth-order Runge-Kutta (Sec. 3) or an adaptive Dormand-Prince 5(4) pair,
+ * termination at the horizon or an escape radius (Sec. 4's benchmark
+ * workload), equatorial-crossing records, redshift and constants of motion.
+ *
+ * Units G = c = M = 1.  Every call returns a kh_status (0 = OK).  Per-geodesic
+ * numerical failure is a result (status KH_FAILED), not a call error.
+ *
+ * Memory: every array in kh_state is caller-owned DEVICE memory, contiguous,
+ * 8-byte aligned (4-byte for int32), laid out structure-of-arrays as stated.
+ * The library never frees or reallocates caller memory.  A kh_ctx owns only
+ * its own scratch (work-queue counters, camera table) and is not thread-safe:
+ * use one context per concurrently used stream.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ * kh_init_*, kh_integrate and kh_rhs are asynchronous with respect to the host;
+ * kh_read_state and kh_stats synchronise the stream and report asynchronous
+ * faults of earlier work on it.  Argument errors are detected on the host
+ * before any launch and return KH_EINVAL with a message in kh_last_error.
+ */
+#ifndef KERRHIP_H
+#define KERRHIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KH_OK = 0,
+  KH_EINVAL = -1,       /* bad argument (checked before any launch) */
+  KH_EHIP = -2,         /* HIP runtime error; text in kh_last_error */
+  KH_EUNSUPPORTED = -3, /* valid but unsupported combination */
+  KH_ENOMEM = -4        /* context scratch allocation failed */
+} kh_status;
+
+/* Per-geodesic status (kh_state.status). */
+enum {
+  KH_ACTIVE = 0,    /* still integrating */
+  KH_CAPTURED = 1,  /* r < r_h_factor * r_H after an accepted step */
+  KH_ESCAPED = 2,   /* r > r_escape and dr/dlambda > 0 after an accepted step */
+  KH_T_END = 3,     /* landed on x^0 = t_end (time-like runs) */
+  KH_MAX_STEPS = 4, /* paused after max_steps accepted steps; resumable */
+  KH_FAILED = 5     /* NaN state, step-size underflow or invalid initial data */
+};
+
+/* Geodesic kind (kh_state.kind).  Null rays are traced future-directed in the
+ * chart with spin -a (the time reverse of the physical photon, which keeps the
+ * Boyer-Lindquist spatial path and stays regular at the future horizon of the
+ * ingoing chart); time-like geodesics run forward in the chart with spin +a. */
+enum { KH_NULL = 0, KH_TIMELIKE = 1 };
+
+enum { KH_RK4 = 0, KH_DOPRI5 = 1 };              /* kh_params.method */
+enum { KH_P64 = 0, KH_P32 = 1, KH_PMIXED = 2 };  /* kh_params.precision */
+enum { KH_RHS_FACTORED = 0, KH_RHS_PAPER = 1 };  /* kh_params.rhs_form */
+
+typedef struct kh_ctx kh_ctx;
+
+/* An image plane (Sec. 4: rays start on an image at large radius and are
+ * integrated backwards toward the hole).  Observer direction
+ * n = (sin incl, 0, cos incl); screen axes e_alpha = (0, 1, 0),
+ * e_beta = (-cos incl, 0, sin incl).  Pixel (row, col) has
+ * alpha = alpha_min + (col + 1/2)(alpha_max - alpha_min)/width and
+ * beta = beta_min + (row + 1/2)(beta_max - beta_min)/height; the ray starts at
+ * r_obs n + alpha e_alpha + beta e_beta with spatial momentum -n and its k^0
+ * from the null condition.  Ray id within the image = row * width + col. */
+typedef struct {
+  double a;      /* physical spin, -1 <= a <= 1 */
+  double r_obs;  /* distance of the image plane (Cartesian), > 0 */
+  double incl;   /* inclination, radians */
+  double alpha_min, alpha_max, beta_min, beta_max;
+  int32_t width, height; /* pixels, > 0 */
+} kh_camera;
+
+/* Geodesic state: caller-owned device arrays, n geodesics. */
+typedef struct {
+  int64_t n;        /* number of geodesics, 1 <= n < 2^31 */
+  double *s;        /* [8][n]: x^0 (= t), x^1..x^3, k^0..k^3 of the chart */
+  double *spin;     /* [n]: physical spin a of each geodesic */
+  int32_t *kind;    /* [n]: KH_NULL or KH_TIMELIKE */
+  double *h;        /* [n]: next DOPRI5 step (<= 0: choose h0); resume data */
+  double *lam;      /* [n]: affine parameter reached */
+  double *phi;      /* [n]: unwrapped Cartesian azimuth atan2(y, x), summed per step */
+  int32_t *status;  /* [n]: KH_ACTIVE ... KH_FAILED */
+  int32_t *n_acc;   /* [n]: accepted steps, cumulative over calls */
+  int32_t *n_rej;   /* [n]: rejected DOPRI5 attempts, cumulative */
+  double *cross;    /* [n][k_cross][3] = (r, phi, g) of equatorial crossings, or NULL */
+  int32_t *n_cross; /* [n]: crossings seen (may exceed k_cross), or NULL */
+  int32_t k_cross;  /* 0..8 crossing slots per geodesic */
+  double *c0;       /* [4][n] = (E, L_z, Q, mu^2) at initialisation, or NULL */
+  double *c1;       /* [4][n] = the same at the end of the last integrate call, or NULL */
+} kh_state;
+
+/* Integration rules.  Defaults (kh_default_params): DOPRI5, FP64,
+ * h_coeff 0.01, rtol = atol = 1e-8, hmax_coeff 0.1, r_h_factor 1.01,
+ * r_escape 1000, t_end 0 (off), r_fp64 3, max_steps 1e6. */
+typedef struct {
+  int32_t method;    /* KH_RK4 (fixed step h = h_coeff * r) or KH_DOPRI5 */
+  int32_t precision; /* KH_P64, KH_P32 (rtol, atol raised to >= 1e-6), KH_PMIXED */
+  int32_t rhs_form;  /* KH_RHS_FACTORED (default) or KH_RHS_PAPER */
+  int32_t k_cross;   /* crossing slots to fill, 0..state.k_cross */
+  double h_coeff;    /* RK4 step / DOPRI5 first step: h = h_coeff * scale(r) */
+  double rtol, atol; /* DOPRI5 tolerances, > 0 */
+  double hmax_coeff; /* DOPRI5 step cap h <= hmax_coeff * scale(r) */
+  double r_h_factor; /* capture radius factor, r_H = 1 + sqrt(1 - a^2) */
+  double r_escape;   /* escape radius */
+  double t_end;      /* > 0: stop and land on x^0 = t_end (DOPRI5 only) */
+  double r_fp64;     /* KH_PMIXED: FP64 right-hand side when any lane of the wave has r < r_fp64 */
+  int64_t max_steps; /* accepted steps per call before KH_MAX_STEPS (> 0) */
+  int32_t block_size;   /* threads per block, multiple of 64 in [64, 1024]; 0 = 256 */
+  int32_t grid_blocks;  /* persistent grid size; 0 = fill the device from the occupancy query */
+  int32_t refill_min;   /* a wave refills once at least this many lanes are idle (1..64); 0 = 16 */
+  int32_t reserved;
+} kh_params;
+/* scale(r) = r for null geodesics and r^{3/2} for time-like ones.  DOPRI5
+ * controller: accept if err <= 1 (err = RMS over the 8 components of
+ * (y5 - y4) / (atol + rtol max(|y_n|, |y_n+1|))), next step
+ * h min(5, max(0.2, 0.9 err^{-1/5})) with no growth right after a rejection,
+ * then capped; a step below 1e-12 h_coeff scale(r) is KH_FAILED. */
+
+/* Algorithmic operation counts, from the right-hand side template instantiated
+ * with a counting scalar (an FMA counts as one mul and one add). */
+typedef struct {
+  int64_t add, mul, div, sqrt; /* per right-hand-side evaluation */
+  int64_t step_add, step_mul;  /* per DOPRI5 attempt (or RK4 step) outside the RHS */
+  int64_t step_div, step_sqrt;
+} kh_flop_counts;
+
+/* Create a context on `device` (HIP ordinal).  *out receives the handle. */
+kh_status kh_create(kh_ctx **out, int device);
+/* Free a context and its scratch.  NULL is accepted. */
+kh_status kh_destroy(kh_ctx *ctx);
+/* Message for the last failed call on ctx (valid until the next call). */
+const char *kh_last_error(const kh_ctx *ctx);
+/* Fill *p with the defaults listed above. */
+void kh_default_params(kh_params *p);
+
+/* Initial states of the rays of n_cams images (host array `cams`), concatenated
+ * in camera order: the rays of camera c occupy ids [off_c, off_c + w_c h_c).
+ * Requires st->n == sum of width*height.  Writes s, spin, kind (KH_NULL),
+ * h = 0, lam = 0, phi = atan2(y, x), status, n_acc = n_rej = 0, n_cross = 0,
+ * cross = NaN and c0. */
+kh_status kh_init_rays(kh_ctx *ctx, const kh_camera *cams, int32_t n_cams, kh_state *st, void *stream);
+
+/* Rays with individual parameters (device arrays [n]): physical spin, inclination,
+ * alpha, beta; common image distance r_obs.  Same outputs as kh_init_rays. */
+kh_status kh_init_rays_list(kh_ctx *ctx, const double *spin, const double *incl, const double *alpha,
+                            const double *beta, double r_obs, kh_state *st, void *stream);
+
+/* Geodesics from positions x3 [3][n] and spins [n] (device).  KH_TIMELIKE: v3
+ * [3][n] is the coordinate velocity dx^i/dt and u^0 = 1/sqrt(-g_ab v^a v^b) with
+ * v^0 = 1 (status KH_FAILED where that norm is not negative).  KH_NULL: v3 is
+ * the spatial momentum and k^0 the future root of the null condition. */
+kh_status kh_init_geodesics(kh_ctx *ctx, int32_t kind, const double *spin, const double *x3, const double *v3,
+                            kh_state *st, void *stream);
+
+/* Integrate every geodesic whose status is KH_ACTIVE or KH_MAX_STEPS until it
+ * terminates or takes max_steps accepted steps in this call.  Asynchronous; no
+ * allocation and no host synchronisation.  Re-entrant: a paused state resumes
+ * exactly (bitwise) where it stopped.  Persistent kernel: each 64-lane wave
+ * takes rays from a global counter and refills retired lanes. */
+kh_status kh_integrate(kh_ctx *ctx, const kh_params *p, kh_state *st, void *stream);
+
+/* Copy rays [first, first + count) to the host: host_s [count][8] (AoS, may be
+ * NULL), host_status [count] (may be NULL).  Synchronises the stream. */
+kh_status kh_read_state(kh_ctx *ctx, const kh_state *st, int64_t first, int64_t count, double *host_s,
+                        int32_t *host_status, void *stream);
+
+/* Reduce the state on the device: out[0..5] = count per status, out[6] = sum of
+ * n_acc, out[7] = sum of n_rej.  Synchronises the stream. */
+kh_status kh_stats(kh_ctx *ctx, const kh_state *st, int64_t out[8], void *stream);
+
+/* Evaluate the right-hand side (the 4 accelerations d k^mu / d lambda) at n
+ * points: spin_chart [n] is the chart spin, s [8][n] the states, acc [4][n]
+ * the output (device arrays).  precision KH_P64 or KH_P32; rhs_form as in
+ * kh_params. */
+kh_status kh_rhs(kh_ctx *ctx, int32_t precision, int32_t rhs_form, const double *spin_chart, const double *s,
+                 double *acc, int64_t n, void *stream);
+
+/* Operation counts of the right-hand side and of one step (host only). */
+kh_status kh_flops(int32_t method, int32_t rhs_form, kh_flop_counts *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KERRHIP_H */

@@ -534,7 +534,7 @@ void run_dopri5(const oracle_params& p, const Geo& G, Ray& R) {
       R.nrej += 1;
       h *= shrink_factor(err);
       after_reject = true;
-      if (h < 1e-12 * p.h_coeff * hscale(G.kind, radius(a, R.y))) {
+      if (!(h >= 1e-12 * p.h_coeff * hscale(G.kind, radius(a, R.y)))) {  // also ends a NaN step
         R.status = ST_FAILED;
         return;
       }

@@ -1,0 +1,238 @@
+"""Python binding of libkerrhip (the C ABI in include/kerrhip.h).
+
+Argument marshalling only: every step of the geodesic integration runs in the
+library's HIP kernels.  PyTorch supplies device memory and streams.  The
+functions ``kh_*`` mirror the C entry points one for one; ``Context`` and
+``State`` are conveniences that allocate the structure-of-arrays tensors and
+raise on error codes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # loaded first so the library binds to the same HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkerrhip.so")
+
+KH_OK, KH_EINVAL, KH_EHIP, KH_EUNSUPPORTED, KH_ENOMEM = 0, -1, -2, -3, -4
+ACTIVE, CAPTURED, ESCAPED, T_END, MAX_STEPS, FAILED = range(6)
+NULL, TIMELIKE = 0, 1
+RK4, DOPRI5 = 0, 1
+P64, P32, PMIXED = 0, 1, 2
+RHS_FACTORED, RHS_PAPER = 0, 1
+
+
+class kh_camera(C.Structure):
+    _fields_ = [("a", C.c_double), ("r_obs", C.c_double), ("incl", C.c_double), ("alpha_min", C.c_double),
+                ("alpha_max", C.c_double), ("beta_min", C.c_double), ("beta_max", C.c_double),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class kh_state(C.Structure):
+    _fields_ = [("n", C.c_int64), ("s", C.c_void_p), ("spin", C.c_void_p), ("kind", C.c_void_p),
+                ("h", C.c_void_p), ("lam", C.c_void_p), ("phi", C.c_void_p), ("status", C.c_void_p),
+                ("n_acc", C.c_void_p), ("n_rej", C.c_void_p), ("cross", C.c_void_p), ("n_cross", C.c_void_p),
+                ("k_cross", C.c_int32), ("c0", C.c_void_p), ("c1", C.c_void_p)]
+
+
+class kh_params(C.Structure):
+    _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("rhs_form", C.c_int32), ("k_cross", C.c_int32),
+                ("h_coeff", C.c_double), ("rtol", C.c_double), ("atol", C.c_double), ("hmax_coeff", C.c_double),
+                ("r_h_factor", C.c_double), ("r_escape", C.c_double), ("t_end", C.c_double),
+                ("r_fp64", C.c_double), ("max_steps", C.c_int64), ("block_size", C.c_int32),
+                ("grid_blocks", C.c_int32), ("refill_min", C.c_int32), ("reserved", C.c_int32)]
+
+
+class kh_flop_counts(C.Structure):
+    _fields_ = [("add", C.c_int64), ("mul", C.c_int64), ("div", C.c_int64), ("sqrt", C.c_int64),
+                ("step_add", C.c_int64), ("step_mul", C.c_int64), ("step_div", C.c_int64),
+                ("step_sqrt", C.c_int64)]
+
+
+EXPORTS = ["kh_create", "kh_destroy", "kh_last_error", "kh_default_params", "kh_init_rays", "kh_init_rays_list",
+           "kh_init_geodesics", "kh_integrate", "kh_read_state", "kh_stats", "kh_rhs", "kh_flops"]
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(hipcc --offload-arch=gfx950); there is no fallback path")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        P = C.POINTER
+        L.kh_create.argtypes = [P(vp), C.c_int]
+        L.kh_destroy.argtypes = [vp]
+        L.kh_last_error.argtypes = [vp]
+        L.kh_last_error.restype = C.c_char_p
+        L.kh_default_params.argtypes = [P(kh_params)]
+        L.kh_default_params.restype = None
+        L.kh_init_rays.argtypes = [vp, P(kh_camera), i32, P(kh_state), vp]
+        L.kh_init_rays_list.argtypes = [vp, vp, vp, vp, vp, d, P(kh_state), vp]
+        L.kh_init_geodesics.argtypes = [vp, i32, vp, vp, vp, P(kh_state), vp]
+        L.kh_integrate.argtypes = [vp, P(kh_params), P(kh_state), vp]
+        L.kh_read_state.argtypes = [vp, P(kh_state), i64, i64, vp, vp, vp]
+        L.kh_stats.argtypes = [vp, P(kh_state), P(i64), vp]
+        L.kh_rhs.argtypes = [vp, i32, i32, vp, vp, vp, i64, vp]
+        L.kh_flops.argtypes = [i32, i32, P(kh_flop_counts)]
+        for name in EXPORTS:
+            if name not in ("kh_last_error", "kh_default_params"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class KerrHipError(RuntimeError):
+    pass
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# One-for-one entry points.
+# ---------------------------------------------------------------------------
+def kh_default_params(**overrides) -> kh_params:
+    p = kh_params()
+    lib().kh_default_params(C.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def kh_flops(method=DOPRI5, rhs_form=RHS_FACTORED) -> dict:
+    out = kh_flop_counts()
+    rc = lib().kh_flops(method, rhs_form, C.byref(out))
+    if rc != KH_OK:
+        raise KerrHipError(f"kh_flops failed ({rc})")
+    return {f: getattr(out, f) for f, _ in kh_flop_counts._fields_}
+
+
+class Context:
+    """A library context bound to one device (``kh_create`` / ``kh_destroy``)."""
+
+    def __init__(self, device: int = 0):
+        self.handle = C.c_void_p()
+        rc = lib().kh_create(C.byref(self.handle), device)
+        if rc != KH_OK:
+            raise KerrHipError(f"kh_create failed ({rc})")
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().kh_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != KH_OK:
+            msg = lib().kh_last_error(self.handle)
+            raise KerrHipError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+    def kh_init_rays(self, cams, st: "State", stream=None):
+        arr = (kh_camera * len(cams))(*cams)
+        self._check(lib().kh_init_rays(self.handle, arr, len(cams), C.byref(st.c), _stream(stream)), "kh_init_rays")
+
+    def kh_init_rays_list(self, spin, incl, alpha, beta, r_obs, st: "State", stream=None):
+        for t in (spin, incl, alpha, beta):
+            _check_vec(t, st.n)
+        self._check(lib().kh_init_rays_list(self.handle, spin.data_ptr(), incl.data_ptr(), alpha.data_ptr(),
+                                            beta.data_ptr(), float(r_obs), C.byref(st.c), _stream(stream)),
+                    "kh_init_rays_list")
+
+    def kh_init_geodesics(self, kind, spin, x3, v3, st: "State", stream=None):
+        _check_vec(spin, st.n)
+        for t in (x3, v3):
+            if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != (3, st.n) or not t.is_contiguous():
+                raise ValueError("x3, v3 must be contiguous float64 CUDA tensors of shape (3, n)")
+        self._check(lib().kh_init_geodesics(self.handle, kind, spin.data_ptr(), x3.data_ptr(), v3.data_ptr(),
+                                            C.byref(st.c), _stream(stream)), "kh_init_geodesics")
+
+    def kh_integrate(self, params: kh_params, st: "State", stream=None):
+        self._check(lib().kh_integrate(self.handle, C.byref(params), C.byref(st.c), _stream(stream)),
+                    "kh_integrate")
+
+    def kh_read_state(self, st: "State", first=0, count=None, stream=None):
+        import numpy as np
+
+        count = st.n - first if count is None else count
+        hs = np.zeros((count, 8))
+        hst = np.zeros(count, np.int32)
+        self._check(lib().kh_read_state(self.handle, C.byref(st.c), first, count, hs.ctypes.data,
+                                        hst.ctypes.data, _stream(stream)), "kh_read_state")
+        return hs, hst
+
+    def kh_stats(self, st: "State", stream=None):
+        out = (C.c_int64 * 8)()
+        self._check(lib().kh_stats(self.handle, C.byref(st.c), out, _stream(stream)), "kh_stats")
+        v = list(out)
+        return dict(status_counts=v[:6], n_acc=v[6], n_rej=v[7])
+
+    def kh_rhs(self, precision, rhs_form, spin_chart, s, stream=None):
+        n = spin_chart.numel()
+        _check_vec(spin_chart, n)
+        if s.dtype != torch.float64 or tuple(s.shape) != (8, n) or not s.is_contiguous() or not s.is_cuda:
+            raise ValueError("s must be a contiguous float64 CUDA tensor of shape (8, n)")
+        acc = torch.empty((4, n), dtype=torch.float64, device=s.device)
+        self._check(lib().kh_rhs(self.handle, precision, rhs_form, spin_chart.data_ptr(), s.data_ptr(),
+                                 acc.data_ptr(), n, _stream(stream)), "kh_rhs")
+        return acc
+
+
+def _check_vec(t, n):
+    if t.dtype != torch.float64 or not t.is_cuda or t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous float64 CUDA tensor with {n} elements")
+
+
+class State:
+    """Structure-of-arrays geodesic state in device memory (torch tensors)."""
+
+    def __init__(self, n: int, k_cross: int = 0, constants: bool = True, device="cuda"):
+        if n < 1:
+            raise ValueError("n must be >= 1")
+        f64 = dict(dtype=torch.float64, device=device)
+        i32 = dict(dtype=torch.int32, device=device)
+        self.n = n
+        self.k_cross = k_cross
+        self.s = torch.zeros((8, n), **f64)
+        self.spin = torch.zeros(n, **f64)
+        self.kind = torch.zeros(n, **i32)
+        self.h = torch.zeros(n, **f64)
+        self.lam = torch.zeros(n, **f64)
+        self.phi = torch.zeros(n, **f64)
+        self.status = torch.zeros(n, **i32)
+        self.n_acc = torch.zeros(n, **i32)
+        self.n_rej = torch.zeros(n, **i32)
+        self.cross = torch.full((n, k_cross, 3), float("nan"), **f64) if k_cross > 0 else None
+        self.n_cross = torch.zeros(n, **i32) if k_cross > 0 else None
+        self.c0 = torch.zeros((4, n), **f64) if constants else None
+        self.c1 = torch.zeros((4, n), **f64) if constants else None
+        p = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        self.c = kh_state(n, p(self.s), p(self.spin), p(self.kind), p(self.h), p(self.lam), p(self.phi),
+                          p(self.status), p(self.n_acc), p(self.n_rej), p(self.cross), p(self.n_cross), k_cross,
+                          p(self.c0), p(self.c1))
+
+    def numpy(self) -> dict:
+        """Host copy of every array (for checks; synchronises)."""
+        out = {}
+        for name in ("s", "spin", "kind", "h", "lam", "phi", "status", "n_acc", "n_rej", "cross", "n_cross", "c0",
+                     "c1"):
+            t = getattr(self, name)
+            out[name] = t.cpu().numpy() if t is not None else None
+        return out

@@ -1,0 +1,976 @@
+// kerrhip.hip -- MI355X (gfx950) kernels and the C ABI declared in include/kerrhip.h.
+//
+// One geodesic per lane.  The integrate kernel is persistent: every 64-lane
+// wave takes ray ids from a global counter (one atomic per refill, lane
+// offsets from mbcnt over the ballot of idle lanes), integrates them with
+// register-resident Runge-Kutta stages, writes a ray back the moment it
+// terminates and refills the freed lanes, so uneven step counts (tens to
+// thousands of steps per ray) do not leave lanes idle until the tail.
+// State is structure-of-arrays in HBM (coalesced loads of consecutive ray
+// ids); the arithmetic is VALU (no contraction here, so no MFMA).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "kerrhip.h"
+#include "ks_math.hpp"
+#include "steppers.hpp"
+
+using namespace kh;
+
+// The Python binding mirrors these layouts with ctypes.
+static_assert(sizeof(kh_camera) == 64, "kh_camera layout");
+static_assert(sizeof(kh_params) == 104, "kh_params layout");
+static_assert(sizeof(kh_state) == 120, "kh_state layout");
+
+namespace {
+
+constexpr int kQueueSlots = 4;  // work-queue counters per context
+
+struct KState {
+  int64_t n;
+  double* s;
+  double* spin;
+  int32_t* kind;
+  double* h;
+  double* lam;
+  double* phi;
+  int32_t* status;
+  int32_t* n_acc;
+  int32_t* n_rej;
+  double* cross;
+  int32_t* n_cross;
+  int32_t k_cross;
+  double* c0;
+  double* c1;
+};
+
+struct KParams {
+  double h_coeff, rtol, atol, hmax_coeff, r_h_factor, r_escape, t_end, r_fp64;
+  int64_t max_steps;
+  int32_t k_cross;
+  int32_t refill_min;
+};
+
+KState to_k(const kh_state* st) {
+  KState k;
+  k.n = st->n;
+  k.s = st->s;
+  k.spin = st->spin;
+  k.kind = st->kind;
+  k.h = st->h;
+  k.lam = st->lam;
+  k.phi = st->phi;
+  k.status = st->status;
+  k.n_acc = st->n_acc;
+  k.n_rej = st->n_rej;
+  k.cross = st->cross;
+  k.n_cross = st->n_cross;
+  k.k_cross = st->k_cross;
+  k.c0 = st->c0;
+  k.c1 = st->c1;
+  return k;
+}
+
+__device__ inline double hscale(int kind, double r) { return kind == KH_TIMELIKE ? r * sqrt(r) : r; }
+
+__device__ inline double r_horizon(double a) {
+  const double q = 1.0 - a * a;
+  return 1.0 + sqrt(q > 0.0 ? q : 0.0);
+}
+
+// Growth / shrink factors of the step-size controller.
+template <typename T>
+__device__ inline T grow_factor(T err, bool after_reject) {
+  T fac;
+  if (err == T(0))
+    fac = T(5);
+  else {
+    fac = T(0.9) * pow(err, T(-0.2));
+    fac = fac < T(0.2) ? T(0.2) : fac;
+    fac = fac > T(5) ? T(5) : fac;
+  }
+  if (after_reject && fac > T(1)) fac = T(1);
+  return fac;
+}
+template <typename T>
+__device__ inline T shrink_factor(T err) {
+  if (err != err) return T(0.2);
+  const T fac = T(0.9) * pow(err, T(-0.2));
+  return fac < T(0.2) ? T(0.2) : fac;
+}
+
+// ---------------------------------------------------------------------------
+// Work-queue helpers.
+// ---------------------------------------------------------------------------
+__global__ void k_reset_counters(unsigned long long* q, int n) {
+  if (threadIdx.x < n) q[threadIdx.x] = 0ull;
+}
+
+// Grab up to popcount(idle) consecutive ray ids for the idle lanes of this
+// wave.  Returns the lane's new id, or -1.  Wave-uniform call.
+__device__ inline int64_t wave_grab(unsigned long long idle, unsigned long long* qctr, int64_t n, bool& exhausted) {
+  const int cnt = __popcll(idle);
+  const int leader = __ffsll((long long)idle) - 1;
+  const int lane = __lane_id();
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(qctr, (unsigned long long)cnt);
+  base = __shfl(base, leader);
+  if (base + (unsigned long long)cnt >= (unsigned long long)n) exhausted = true;
+  if (!((idle >> lane) & 1ull)) return -1;
+  const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(idle >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)idle, 0u));
+  const unsigned long long id = base + rank;
+  return id < (unsigned long long)n ? (int64_t)id : -1;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent integrate kernel.
+// METHOD: KH_RK4 / KH_DOPRI5.  PREC: KH_P64 / KH_P32 / KH_PMIXED.
+// FORM: right-hand-side evaluation (KH_RHS_FACTORED / KH_RHS_PAPER).
+// ---------------------------------------------------------------------------
+template <int METHOD, int PREC, int FORM>
+__global__ void __launch_bounds__(256) k_integrate(KParams P, KState S, unsigned long long* qctr) {
+  using TS = typename std::conditional<PREC == KH_P32, float, double>::type;  // state / stages
+  using TF = typename std::conditional<PREC == KH_P64, double, float>::type;  // fast right-hand side
+
+  const int64_t n = S.n;
+  int64_t ray = -1;
+  bool exhausted = false;
+  bool fresh = false;
+
+  TS x[4], k[4], a1[4];
+  TS r_cur = TS(0), rdot_cur = TS(0);
+  TS a_c = TS(0);
+  double a_phys = 0.0, h = 0.0, lam = 0.0, phi = 0.0;
+  int kind = 0, nacc = 0, nrej = 0, ncross = 0, status = KH_ACTIVE;
+  int64_t steps = 0, tries = 0;
+  bool after_reject = false;
+
+  while (true) {
+    // ---- refill idle lanes (wave-uniform decision) ----
+    const unsigned long long idle = __ballot(ray < 0);
+    if (!exhausted && idle != 0ull && (__popcll(idle) >= P.refill_min || idle == ~0ull)) {
+      const int64_t id = wave_grab(idle, qctr, n, exhausted);
+      if (ray < 0 && id >= 0) {
+        const int st = S.status[id];
+        if (st == KH_ACTIVE || st == KH_MAX_STEPS) {
+          ray = id;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            x[c] = (TS)S.s[c * n + id];
+            k[c] = (TS)S.s[(4 + c) * n + id];
+          }
+          kind = S.kind[id];
+          a_phys = S.spin[id];
+          a_c = (TS)(kind == KH_NULL ? -a_phys : a_phys);
+          h = S.h[id];
+          lam = S.lam[id];
+          phi = S.phi[id];
+          nacc = S.n_acc[id];
+          nrej = S.n_rej[id];
+          ncross = S.n_cross ? S.n_cross[id] : 0;
+          status = KH_ACTIVE;
+          steps = 0;
+          tries = 0;
+          after_reject = false;
+          fresh = true;
+        }
+      }
+    }
+    if (__ballot(ray >= 0) == 0ull) {
+      if (exhausted) break;
+      continue;
+    }
+    if (ray < 0) continue;
+
+    // ---- first-stage acceleration of a freshly loaded ray ----
+    if (fresh || METHOD == KH_RK4) {
+      const Accel<TS> ra = rhs<FORM, TS>(a_c, x, k);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a1[c] = ra.a[c];
+      r_cur = ra.r;
+      rdot_cur = ra.rdot;
+      if (METHOD == KH_DOPRI5 && fresh && !(h > 0.0)) {
+        h = P.h_coeff * hscale(kind, (double)r_cur);
+        const double hm = P.hmax_coeff * hscale(kind, (double)r_cur);
+        h = h < hm ? h : hm;
+      }
+      fresh = false;
+    }
+
+    if (METHOD == KH_RK4) {
+      // Termination of the previous step is decided here, with r from a1.
+      if (steps > 0) {
+        bool bad = false;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bad = bad || (x[c] != x[c]) || (k[c] != k[c]);
+        if (bad)
+          status = KH_FAILED;
+        else if ((double)r_cur < P.r_h_factor * r_horizon((double)a_c))
+          status = KH_CAPTURED;
+        else if ((double)r_cur > P.r_escape && rdot_cur > TS(0))
+          status = KH_ESCAPED;
+        else if (steps >= P.max_steps)
+          status = KH_MAX_STEPS;
+      }
+      if (status == KH_ACTIVE) {
+        const TS hs = (TS)(P.h_coeff) * r_cur;
+        TS xn[4], kn[4];
+        if (PREC == KH_PMIXED && __ballot(r_cur < (TS)P.r_fp64) == 0ull)
+          rk4_step<FORM, TS, TF>(a_c, x, k, a1, hs, xn, kn);
+        else
+          rk4_step<FORM, TS, TS>(a_c, x, k, a1, hs, xn, kn);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          x[c] = xn[c];
+          k[c] = kn[c];
+        }
+        lam += (double)hs;
+        ++nacc;
+        ++steps;
+        h = (double)hs;
+        continue;
+      }
+    } else {
+      TS xn[4], kn[4], a7[4], r_new, rdot_new;
+      const TS hs = (TS)h;
+      const TS rtol = (TS)P.rtol, atol = (TS)P.atol;
+      TS err;
+      if (PREC == KH_PMIXED && __ballot(r_cur < (TS)P.r_fp64) == 0ull)
+        err = dp5_attempt<FORM, TS, TF>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
+      else
+        err = dp5_attempt<FORM, TS, TS>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
+
+      if (err <= TS(1)) {
+        ++nacc;
+        ++steps;
+        bool bad = false;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bad = bad || (xn[c] != xn[c]) || (kn[c] != kn[c]);
+        const double lam_old = lam;
+        lam += h;
+        if (bad) {
+          status = KH_FAILED;
+        } else {
+          if (P.k_cross > 0) {
+            // Unwrapped azimuth and equatorial crossings between the two nodes.
+            const double x0 = x[1], y0 = x[2], z0 = x[3];
+            const double x1 = xn[1], y1 = xn[2], z1 = xn[3];
+            const double phi0 = phi;
+            phi = phi0 + atan2(x0 * y1 - y0 * x1, x0 * x1 + y0 * y1);
+            if ((z0 < 0.0 && z1 > 0.0) || (z0 > 0.0 && z1 < 0.0) || (z1 == 0.0 && z0 != 0.0)) {
+              const double th = hermite_zero(z0, (double)k[3], z1, (double)kn[3], h);
+              const double xc = herm(th, x0, (double)k[1], x1, (double)kn[1], h);
+              const double yc = herm(th, y0, (double)k[2], y1, (double)kn[2], h);
+              const double ac = (double)a_c;
+              const double q = xc * xc + yc * yc - ac * ac;
+              const double rc = sqrt(q > 0.0 ? q : 0.0);
+              const double phic = phi0 + atan2(x0 * yc - y0 * xc, x0 * xc + y0 * yc);
+              double xd[4], kd[4];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                xd[c] = (double)xn[c];
+                kd[c] = (double)kn[c];
+              }
+              const double xi = photon_xi(ac, xd, kd, kind == KH_NULL);
+              const double g = redshift(rc, xi, a_phys);
+              if (ncross < S.k_cross && ncross < P.k_cross) {
+                double* cr = S.cross + ((int64_t)ray * S.k_cross + ncross) * 3;
+                cr[0] = rc;
+                cr[1] = phic;
+                cr[2] = g;
+              }
+              ++ncross;
+            }
+          }
+          if ((double)r_new < P.r_h_factor * r_horizon((double)a_c))
+            status = KH_CAPTURED;
+          else if ((double)r_new > P.r_escape && rdot_new > TS(0))
+            status = KH_ESCAPED;
+          else if (P.t_end > 0.0 && (double)xn[0] >= P.t_end) {
+            // Land on t = t_end with the cubic Hermite interpolant of t(lambda);
+            // positions use dx/dlambda = k, momenta use dk/dlambda = acc.
+            const double th = hermite_zero((double)x[0] - P.t_end, (double)k[0], (double)xn[0] - P.t_end,
+                                           (double)kn[0], h);
+            TS xl[4], kl[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              xl[c] = (TS)herm(th, (double)x[c], (double)k[c], (double)xn[c], (double)kn[c], h);
+              kl[c] = (TS)herm(th, (double)k[c], (double)a1[c], (double)kn[c], (double)a7[c], h);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              xn[c] = xl[c];
+              kn[c] = kl[c];
+            }
+            lam = lam_old + th * h;
+            status = KH_T_END;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          x[c] = xn[c];
+          k[c] = kn[c];
+          a1[c] = a7[c];
+        }
+        r_cur = r_new;
+        rdot_cur = rdot_new;
+        if (status == KH_ACTIVE) {
+          h = h * (double)grow_factor<TS>(err, after_reject);
+          const double hm = P.hmax_coeff * hscale(kind, (double)r_cur);
+          h = h < hm ? h : hm;
+          after_reject = false;
+          if (steps >= P.max_steps) status = KH_MAX_STEPS;
+        }
+      } else {
+        ++nrej;
+        h = h * (double)shrink_factor<TS>(err);
+        after_reject = true;
+        // written so that a NaN step size also ends the ray
+        if (!(h >= 1e-12 * P.h_coeff * hscale(kind, (double)r_cur))) status = KH_FAILED;
+      }
+      if (status == KH_ACTIVE && ++tries > 4 * P.max_steps + 1000) status = KH_MAX_STEPS;
+    }
+
+    if (status != KH_ACTIVE) {
+      // ---- retire: write the ray back and free the lane ----
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        S.s[c * n + ray] = (double)x[c];
+        S.s[(4 + c) * n + ray] = (double)k[c];
+      }
+      S.h[ray] = h;
+      S.lam[ray] = lam;
+      S.phi[ray] = phi;
+      S.status[ray] = status;
+      S.n_acc[ray] = nacc;
+      S.n_rej[ray] = nrej;
+      if (S.n_cross) S.n_cross[ray] = ncross;
+      if (S.c1) {
+        double xd[4], kd[4], cst[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          xd[c] = (double)x[c];
+          kd[c] = (double)k[c];
+        }
+        constants((double)a_c, xd, kd, cst);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) S.c1[q * n + ray] = cst[q];
+      }
+      ray = -1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial data.
+// ---------------------------------------------------------------------------
+__device__ inline void finish_init(KState S, int64_t i, const double y[8], double a_phys, int kind, bool ok) {
+  const int64_t n = S.n;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) S.s[c * n + i] = y[c];
+  S.spin[i] = a_phys;
+  S.kind[i] = kind;
+  S.h[i] = 0.0;
+  S.lam[i] = 0.0;
+  S.phi[i] = atan2(y[2], y[1]);
+  S.status[i] = ok ? KH_ACTIVE : KH_FAILED;
+  S.n_acc[i] = 0;
+  S.n_rej[i] = 0;
+  if (S.n_cross) S.n_cross[i] = 0;
+  if (S.cross)
+    for (int j = 0; j < 3 * S.k_cross; ++j) S.cross[i * 3 * S.k_cross + j] = __builtin_nan("");
+  if (S.c0) {
+    double cst[4];
+    constants(kind == KH_NULL ? -a_phys : a_phys, y, y + 4, cst);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) S.c0[q * n + i] = cst[q];
+  }
+}
+
+__device__ inline void camera_ray(double a_phys, double d, double incl, double al, double be, double y[8], bool* ok) {
+  double si, ci;
+  sincos(incl, &si, &ci);
+  y[0] = 0.0;
+  y[1] = d * si - be * ci;
+  y[2] = al;
+  y[3] = d * ci + be * si;
+  y[4] = 0.0;
+  y[5] = -si;
+  y[6] = 0.0;
+  y[7] = -ci;
+  // traced future-directed in the chart with spin -a
+  y[4] = null_k0(-a_phys, y, y + 4, ok);
+  *ok = *ok && (y[4] == y[4]);
+}
+
+__global__ void k_init_rays(const kh_camera* cams, const int64_t* offs, int n_cams, KState S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  int lo = 0, hi = n_cams - 1;  // last camera with offs[c] <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const kh_camera cam = cams[lo];
+  const int64_t p = i - offs[lo];
+  const int64_t row = p / cam.width, col = p % cam.width;
+  const double al = cam.alpha_min + (col + 0.5) * (cam.alpha_max - cam.alpha_min) / cam.width;
+  const double be = cam.beta_min + (row + 0.5) * (cam.beta_max - cam.beta_min) / cam.height;
+  double y[8];
+  bool ok;
+  camera_ray(cam.a, cam.r_obs, cam.incl, al, be, y, &ok);
+  finish_init(S, i, y, cam.a, KH_NULL, ok);
+}
+
+__global__ void k_init_rays_list(const double* spin, const double* incl, const double* alpha, const double* beta,
+                                 double r_obs, KState S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  double y[8];
+  bool ok;
+  camera_ray(spin[i], r_obs, incl[i], alpha[i], beta[i], y, &ok);
+  finish_init(S, i, y, spin[i], KH_NULL, ok);
+}
+
+__global__ void k_init_geodesics(int kind, const double* spin, const double* x3, const double* v3, KState S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = S.n;
+  if (i >= n) return;
+  const double a = spin[i];
+  double y[8] = {0.0, x3[i], x3[n + i], x3[2 * n + i], 0.0, v3[i], v3[n + i], v3[2 * n + i]};
+  bool ok;
+  if (kind == KH_TIMELIKE) {
+    const double v[3] = {y[5], y[6], y[7]};
+    const double u0 = timelike_u0(a, y, v, &ok);
+    y[4] = u0;
+    y[5] *= u0;
+    y[6] *= u0;
+    y[7] *= u0;
+  } else {
+    y[4] = null_k0(-a, y, y + 4, &ok);
+  }
+  finish_init(S, i, y, a, kind, ok && (y[4] == y[4]));
+}
+
+// ---------------------------------------------------------------------------
+// Point evaluation of the right-hand side and device-side statistics.
+// ---------------------------------------------------------------------------
+template <typename T, int FORM>
+__global__ void k_rhs(const double* spin_chart, const double* s, double* acc, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T x[4], k[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    x[c] = (T)s[c * n + i];
+    k[c] = (T)s[(4 + c) * n + i];
+  }
+  const Accel<T> ra = rhs<FORM, T>((T)spin_chart[i], x, k);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c * n + i] = (double)ra.a[c];
+}
+
+__global__ void k_stats(const int32_t* status, const int32_t* n_acc, const int32_t* n_rej, int64_t n,
+                        unsigned long long* out) {
+  __shared__ unsigned long long part[8];
+  if (threadIdx.x < 8) part[threadIdx.x] = 0ull;
+  __syncthreads();
+  unsigned long long loc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int st = status[i];
+    if (st >= 0 && st < 6) loc[st] += 1ull;
+    loc[6] += (unsigned long long)n_acc[i];
+    loc[7] += (unsigned long long)n_rej[i];
+  }
+  for (int q = 0; q < 8; ++q) {
+    unsigned long long v = loc[q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&part[q], v);
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) atomicAdd(&out[threadIdx.x], part[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side operation counter for kh_flops.
+// ---------------------------------------------------------------------------
+struct Tally {
+  int64_t add = 0, mul = 0, div = 0, sqrt = 0;
+};
+thread_local Tally* g_tally = nullptr;
+
+struct Cnt {
+  double v;
+  Cnt() : v(0) {}
+  Cnt(double d) : v(d) {}
+};
+inline Cnt operator+(Cnt a, Cnt b) {
+  ++g_tally->add;
+  return Cnt(a.v + b.v);
+}
+inline Cnt operator-(Cnt a, Cnt b) {
+  ++g_tally->add;
+  return Cnt(a.v - b.v);
+}
+inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
+inline Cnt operator*(Cnt a, Cnt b) {
+  ++g_tally->mul;
+  return Cnt(a.v * b.v);
+}
+inline Cnt operator/(Cnt a, Cnt b) {
+  ++g_tally->div;
+  return Cnt(a.v / b.v);
+}
+inline bool operator>=(Cnt a, Cnt b) { return a.v >= b.v; }
+inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
+// found by argument-dependent lookup from the templates in namespace kh
+inline Cnt ksqrt(Cnt x) {
+  ++g_tally->sqrt;
+  return Cnt(std::sqrt(x.v));
+}
+inline Cnt kabs(Cnt x) { return Cnt(std::fabs(x.v)); }
+inline Cnt kmax(Cnt x, Cnt y) { return x.v > y.v ? x : y; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context and C ABI.
+// ---------------------------------------------------------------------------
+struct kh_ctx {
+  int device = 0;
+  int n_cu = 0;
+  unsigned long long* d_queue = nullptr;  // kQueueSlots counters
+  unsigned long long* d_stats = nullptr;  // 8 counters
+  kh_camera* d_cams = nullptr;
+  int64_t* d_offs = nullptr;
+  int cam_cap = 0;
+  kh_camera* h_cams = nullptr;  // pinned staging
+  int64_t* h_offs = nullptr;
+  hipEvent_t cam_evt = nullptr;
+  std::string err;
+};
+
+namespace {
+
+kh_status fail(kh_ctx* c, kh_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+kh_status hip_fail(kh_ctx* c, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(c, KH_EHIP, m);
+}
+
+#define KH_HIP(ctx, call)                                 \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Device pointer check: a host pointer handed to a kernel would fault the GPU.
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+kh_status check_state(kh_ctx* ctx, const kh_state* st, bool need_cross) {
+  if (!st) return fail(ctx, KH_EINVAL, "state is NULL");
+  if (st->n < 1 || st->n >= (int64_t(1) << 31)) return fail(ctx, KH_EINVAL, "state.n must be in [1, 2^31)");
+  if (st->k_cross < 0 || st->k_cross > 8) return fail(ctx, KH_EINVAL, "state.k_cross must be in [0, 8]");
+  const void* d8[] = {st->s, st->spin, st->h, st->lam, st->phi};
+  for (const void* p : d8)
+    if (!p || !aligned(p, 8) || !is_device_ptr(p))
+      return fail(ctx, KH_EINVAL, "state arrays s, spin, h, lam, phi must be 8-byte aligned device memory");
+  const void* d4[] = {st->kind, st->status, st->n_acc, st->n_rej};
+  for (const void* p : d4)
+    if (!p || !aligned(p, 4) || !is_device_ptr(p))
+      return fail(ctx, KH_EINVAL, "state arrays kind, status, n_acc, n_rej must be 4-byte aligned device memory");
+  const void* opt8[] = {st->c0, st->c1, st->cross};
+  for (const void* p : opt8)
+    if (p && (!aligned(p, 8) || !is_device_ptr(p)))
+      return fail(ctx, KH_EINVAL, "state arrays c0, c1, cross must be NULL or 8-byte aligned device memory");
+  if (st->n_cross && (!aligned(st->n_cross, 4) || !is_device_ptr(st->n_cross)))
+    return fail(ctx, KH_EINVAL, "state.n_cross must be NULL or 4-byte aligned device memory");
+  if (need_cross && st->k_cross > 0 && (!st->cross || !st->n_cross))
+    return fail(ctx, KH_EINVAL, "state.k_cross > 0 requires cross and n_cross");
+  return KH_OK;
+}
+
+kh_status set_device(kh_ctx* ctx) {
+  KH_HIP(ctx, hipSetDevice(ctx->device));
+  return KH_OK;
+}
+
+template <int M, int P, int F>
+void* kernel_ptr() {
+  return reinterpret_cast<void*>(&k_integrate<M, P, F>);
+}
+
+void* pick_kernel(int method, int prec, int form) {
+#define KH_PICK(M, P, F) \
+  if (method == M && prec == P && form == F) return kernel_ptr<M, P, F>();
+  KH_PICK(KH_RK4, KH_P64, KH_RHS_FACTORED)
+  KH_PICK(KH_RK4, KH_P32, KH_RHS_FACTORED)
+  KH_PICK(KH_RK4, KH_PMIXED, KH_RHS_FACTORED)
+  KH_PICK(KH_RK4, KH_P64, KH_RHS_PAPER)
+  KH_PICK(KH_RK4, KH_P32, KH_RHS_PAPER)
+  KH_PICK(KH_DOPRI5, KH_P64, KH_RHS_FACTORED)
+  KH_PICK(KH_DOPRI5, KH_P32, KH_RHS_FACTORED)
+  KH_PICK(KH_DOPRI5, KH_PMIXED, KH_RHS_FACTORED)
+  KH_PICK(KH_DOPRI5, KH_P64, KH_RHS_PAPER)
+  KH_PICK(KH_DOPRI5, KH_P32, KH_RHS_PAPER)
+#undef KH_PICK
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+void kh_default_params(kh_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->method = KH_DOPRI5;
+  p->precision = KH_P64;
+  p->rhs_form = KH_RHS_FACTORED;
+  p->k_cross = 0;
+  p->h_coeff = 0.01;
+  p->rtol = 1e-8;
+  p->atol = 1e-8;
+  p->hmax_coeff = 0.1;
+  p->r_h_factor = 1.01;
+  p->r_escape = 1000.0;
+  p->t_end = 0.0;
+  p->r_fp64 = 3.0;
+  p->max_steps = 1000000;
+}
+
+kh_status kh_create(kh_ctx** out, int device) {
+  if (!out) return KH_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return KH_EINVAL;
+  kh_ctx* c = new kh_ctx();
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      hipMalloc(&c->d_queue, kQueueSlots * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&c->d_stats, 8 * sizeof(unsigned long long)) != hipSuccess ||
+      hipEventCreateWithFlags(&c->cam_evt, hipEventDisableTiming) != hipSuccess) {
+    kh_destroy(c);
+    return KH_ENOMEM;
+  }
+  *out = c;
+  return KH_OK;
+}
+
+kh_status kh_destroy(kh_ctx* c) {
+  if (!c) return KH_OK;
+  (void)hipSetDevice(c->device);
+  if (c->cam_evt) (void)hipEventSynchronize(c->cam_evt);
+  if (c->d_queue) (void)hipFree(c->d_queue);
+  if (c->d_stats) (void)hipFree(c->d_stats);
+  if (c->d_cams) (void)hipFree(c->d_cams);
+  if (c->d_offs) (void)hipFree(c->d_offs);
+  if (c->h_cams) (void)hipHostFree(c->h_cams);
+  if (c->h_offs) (void)hipHostFree(c->h_offs);
+  if (c->cam_evt) (void)hipEventDestroy(c->cam_evt);
+  delete c;
+  return KH_OK;
+}
+
+const char* kh_last_error(const kh_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+kh_status kh_init_rays(kh_ctx* ctx, const kh_camera* cams, int32_t n_cams, kh_state* st, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  if (!cams || n_cams < 1) return fail(ctx, KH_EINVAL, "need at least one camera");
+  int64_t total = 0;
+  for (int i = 0; i < n_cams; ++i) {
+    const kh_camera& c = cams[i];
+    if (!(std::fabs(c.a) <= 1.0) || !(c.r_obs > 0.0) || c.width < 1 || c.height < 1 || !std::isfinite(c.incl) ||
+        !std::isfinite(c.alpha_min) || !std::isfinite(c.alpha_max) || !std::isfinite(c.beta_min) ||
+        !std::isfinite(c.beta_max))
+      return fail(ctx, KH_EINVAL, "camera " + std::to_string(i) + ": need |a| <= 1, r_obs > 0, width, height >= 1");
+    total += int64_t(c.width) * c.height;
+  }
+  kh_status s = check_state(ctx, st, false);
+  if (s != KH_OK) return s;
+  if (total != st->n) return fail(ctx, KH_EINVAL, "state.n must equal the total pixel count of the cameras");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  hipStream_t strm = (hipStream_t)stream;
+  if (n_cams > ctx->cam_cap) {
+    KH_HIP(ctx, hipEventSynchronize(ctx->cam_evt));
+    if (ctx->d_cams) KH_HIP(ctx, hipFree(ctx->d_cams));
+    if (ctx->d_offs) KH_HIP(ctx, hipFree(ctx->d_offs));
+    if (ctx->h_cams) KH_HIP(ctx, hipHostFree(ctx->h_cams));
+    if (ctx->h_offs) KH_HIP(ctx, hipHostFree(ctx->h_offs));
+    ctx->d_cams = nullptr;
+    ctx->d_offs = nullptr;
+    ctx->h_cams = nullptr;
+    ctx->h_offs = nullptr;
+    ctx->cam_cap = 0;
+    const int cap = std::max(n_cams, 64);
+    if (hipMalloc(&ctx->d_cams, cap * sizeof(kh_camera)) != hipSuccess ||
+        hipMalloc(&ctx->d_offs, (cap + 1) * sizeof(int64_t)) != hipSuccess ||
+        hipHostMalloc(&ctx->h_cams, cap * sizeof(kh_camera), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&ctx->h_offs, (cap + 1) * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+      return fail(ctx, KH_ENOMEM, "camera table allocation failed");
+    ctx->cam_cap = cap;
+  }
+  // The staging buffers may still feed the previous call's copy.
+  KH_HIP(ctx, hipEventSynchronize(ctx->cam_evt));
+  int64_t off = 0;
+  for (int i = 0; i < n_cams; ++i) {
+    ctx->h_cams[i] = cams[i];
+    ctx->h_offs[i] = off;
+    off += int64_t(cams[i].width) * cams[i].height;
+  }
+  ctx->h_offs[n_cams] = off;
+  KH_HIP(ctx, hipMemcpyAsync(ctx->d_cams, ctx->h_cams, n_cams * sizeof(kh_camera), hipMemcpyHostToDevice, strm));
+  KH_HIP(ctx,
+         hipMemcpyAsync(ctx->d_offs, ctx->h_offs, (n_cams + 1) * sizeof(int64_t), hipMemcpyHostToDevice, strm));
+  KH_HIP(ctx, hipEventRecord(ctx->cam_evt, strm));
+  const KState ks = to_k(st);
+  const int block = 256;
+  const int64_t grid = (st->n + block - 1) / block;
+  hipLaunchKernelGGL(k_init_rays, dim3((unsigned)grid), dim3(block), 0, strm, ctx->d_cams, ctx->d_offs, n_cams, ks);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+kh_status kh_init_rays_list(kh_ctx* ctx, const double* spin, const double* incl, const double* alpha,
+                            const double* beta, double r_obs, kh_state* st, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  kh_status s = check_state(ctx, st, false);
+  if (s != KH_OK) return s;
+  const double* ins[] = {spin, incl, alpha, beta};
+  for (const double* p : ins)
+    if (!p || !aligned(p, 8) || !is_device_ptr(p))
+      return fail(ctx, KH_EINVAL, "spin, incl, alpha, beta must be 8-byte aligned device arrays of length n");
+  if (!(r_obs > 0.0)) return fail(ctx, KH_EINVAL, "r_obs must be > 0");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  const KState ks = to_k(st);
+  const int block = 256;
+  const int64_t grid = (st->n + block - 1) / block;
+  hipLaunchKernelGGL(k_init_rays_list, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)stream, spin, incl, alpha,
+                     beta, r_obs, ks);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+kh_status kh_init_geodesics(kh_ctx* ctx, int32_t kind, const double* spin, const double* x3, const double* v3,
+                            kh_state* st, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  if (kind != KH_NULL && kind != KH_TIMELIKE) return fail(ctx, KH_EINVAL, "kind must be KH_NULL or KH_TIMELIKE");
+  kh_status s = check_state(ctx, st, false);
+  if (s != KH_OK) return s;
+  const double* ins[] = {spin, x3, v3};
+  for (const double* p : ins)
+    if (!p || !aligned(p, 8) || !is_device_ptr(p))
+      return fail(ctx, KH_EINVAL, "spin [n], x3 [3][n], v3 [3][n] must be 8-byte aligned device arrays");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  const KState ks = to_k(st);
+  const int block = 256;
+  const int64_t grid = (st->n + block - 1) / block;
+  hipLaunchKernelGGL(k_init_geodesics, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)stream, (int)kind, spin,
+                     x3, v3, ks);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  if (!p) return fail(ctx, KH_EINVAL, "params is NULL");
+  if (p->method != KH_RK4 && p->method != KH_DOPRI5) return fail(ctx, KH_EINVAL, "unknown method");
+  if (p->precision != KH_P64 && p->precision != KH_P32 && p->precision != KH_PMIXED)
+    return fail(ctx, KH_EINVAL, "unknown precision");
+  if (p->rhs_form != KH_RHS_FACTORED && p->rhs_form != KH_RHS_PAPER) return fail(ctx, KH_EINVAL, "unknown rhs_form");
+  if (!(p->h_coeff > 0.0) || !(p->r_h_factor > 0.0) || !(p->r_escape > 0.0) || p->max_steps < 1)
+    return fail(ctx, KH_EINVAL, "need h_coeff, r_h_factor, r_escape > 0 and max_steps >= 1");
+  if (p->method == KH_DOPRI5 && (!(p->rtol > 0.0) || !(p->atol > 0.0) || !(p->hmax_coeff > 0.0)))
+    return fail(ctx, KH_EINVAL, "DOPRI5 needs rtol, atol, hmax_coeff > 0");
+  if (p->k_cross < 0 || p->k_cross > 8) return fail(ctx, KH_EINVAL, "k_cross must be in [0, 8]");
+  if (p->method == KH_RK4 && (p->k_cross > 0 || p->t_end > 0.0))
+    return fail(ctx, KH_EUNSUPPORTED, "crossings and t_end need the DOPRI5 dense output");
+  if (p->k_cross > 0 && p->t_end > 0.0)
+    return fail(ctx, KH_EUNSUPPORTED, "crossing records and t_end landing are not combined");
+  if (p->rhs_form == KH_RHS_PAPER && p->precision == KH_PMIXED)
+    return fail(ctx, KH_EUNSUPPORTED, "the paper-form right-hand side is built for P64 and P32 only");
+  const int block = p->block_size ? p->block_size : 256;
+  if (block < 64 || block > 256 || block % 64) return fail(ctx, KH_EINVAL, "block_size must be 64, 128, 192 or 256");
+  const int refill = p->refill_min ? p->refill_min : 16;
+  if (refill < 1 || refill > 64) return fail(ctx, KH_EINVAL, "refill_min must be in [1, 64]");
+  if (p->grid_blocks < 0) return fail(ctx, KH_EINVAL, "grid_blocks must be >= 0");
+  kh_status s = check_state(ctx, st, p->k_cross > 0);
+  if (s != KH_OK) return s;
+  if (p->k_cross > st->k_cross) return fail(ctx, KH_EINVAL, "params.k_cross exceeds state.k_cross");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+
+  KParams kp;
+  kp.h_coeff = p->h_coeff;
+  kp.rtol = p->rtol;
+  kp.atol = p->atol;
+  if (p->precision == KH_P32) {  // FP32 cannot honour tolerances near its epsilon
+    kp.rtol = std::max(kp.rtol, 1e-6);
+    kp.atol = std::max(kp.atol, 1e-6);
+  }
+  kp.hmax_coeff = p->hmax_coeff;
+  kp.r_h_factor = p->r_h_factor;
+  kp.r_escape = p->r_escape;
+  kp.t_end = p->t_end;
+  kp.r_fp64 = p->r_fp64;
+  kp.max_steps = p->max_steps;
+  kp.k_cross = p->k_cross;
+  kp.refill_min = refill;
+
+  void* fn = pick_kernel(p->method, p->precision, p->rhs_form);
+  if (!fn) return fail(ctx, KH_EUNSUPPORTED, "no kernel for this method / precision / rhs_form");
+  int grid = p->grid_blocks;
+  if (grid == 0) {
+    int per_cu = 0;
+    KH_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, block, 0));
+    grid = std::max(1, per_cu) * ctx->n_cu;
+  }
+  const int64_t need = (st->n + block - 1) / block;
+  if (grid > need) grid = (int)need;
+  hipStream_t strm = (hipStream_t)stream;
+  unsigned long long* q = ctx->d_queue;
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, strm, q, 1);
+  KH_HIP(ctx, hipGetLastError());
+  const KState ks = to_k(st);
+  void* args[] = {(void*)&kp, (void*)&ks, (void*)&q};
+  KH_HIP(ctx, hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, strm));
+  return KH_OK;
+}
+
+kh_status kh_read_state(kh_ctx* ctx, const kh_state* st, int64_t first, int64_t count, double* host_s,
+                        int32_t* host_status, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  kh_status s = check_state(ctx, st, false);
+  if (s != KH_OK) return s;
+  if (first < 0 || count < 0 || first + count > st->n) return fail(ctx, KH_EINVAL, "range outside the state");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  hipStream_t strm = (hipStream_t)stream;
+  std::vector<double> tmp;
+  if (host_s && count > 0) {
+    tmp.resize(size_t(8) * count);
+    for (int c = 0; c < 8; ++c)
+      KH_HIP(ctx, hipMemcpyAsync(tmp.data() + size_t(c) * count, st->s + c * st->n + first, count * sizeof(double),
+                                 hipMemcpyDeviceToHost, strm));
+  }
+  if (host_status && count > 0)
+    KH_HIP(ctx, hipMemcpyAsync(host_status, st->status + first, count * sizeof(int32_t), hipMemcpyDeviceToHost, strm));
+  KH_HIP(ctx, hipStreamSynchronize(strm));
+  if (host_s)
+    for (int64_t i = 0; i < count; ++i)
+      for (int c = 0; c < 8; ++c) host_s[i * 8 + c] = tmp[size_t(c) * count + i];
+  return KH_OK;
+}
+
+kh_status kh_stats(kh_ctx* ctx, const kh_state* st, int64_t out[8], void* stream) {
+  if (!ctx) return KH_EINVAL;
+  if (!out) return fail(ctx, KH_EINVAL, "out is NULL");
+  kh_status s = check_state(ctx, st, false);
+  if (s != KH_OK) return s;
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  hipStream_t strm = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, strm, ctx->d_stats, 8);
+  const int block = 256;
+  int64_t grid = std::min<int64_t>((st->n + block - 1) / block, 4 * std::max(ctx->n_cu, 1));
+  hipLaunchKernelGGL(k_stats, dim3((unsigned)grid), dim3(block), 0, strm, st->status, st->n_acc, st->n_rej, st->n,
+                     ctx->d_stats);
+  KH_HIP(ctx, hipGetLastError());
+  unsigned long long h[8];
+  KH_HIP(ctx, hipMemcpyAsync(h, ctx->d_stats, sizeof h, hipMemcpyDeviceToHost, strm));
+  KH_HIP(ctx, hipStreamSynchronize(strm));
+  for (int i = 0; i < 8; ++i) out[i] = (int64_t)h[i];
+  return KH_OK;
+}
+
+kh_status kh_rhs(kh_ctx* ctx, int32_t precision, int32_t rhs_form, const double* spin_chart, const double* s,
+                 double* acc, int64_t n, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  if (n < 1 || n >= (int64_t(1) << 31)) return fail(ctx, KH_EINVAL, "n must be in [1, 2^31)");
+  const double* ins[] = {spin_chart, s, acc};
+  for (const double* p : ins)
+    if (!p || !aligned(p, 8) || !is_device_ptr(p)) return fail(ctx, KH_EINVAL, "arrays must be device memory");
+  if (precision != KH_P64 && precision != KH_P32) return fail(ctx, KH_EINVAL, "precision must be KH_P64 or KH_P32");
+  if (rhs_form != KH_RHS_FACTORED && rhs_form != KH_RHS_PAPER) return fail(ctx, KH_EINVAL, "unknown rhs_form");
+  kh_status st = set_device(ctx);
+  if (st != KH_OK) return st;
+  const int block = 256;
+  const dim3 grid((unsigned)((n + block - 1) / block));
+  hipStream_t strm = (hipStream_t)stream;
+  if (precision == KH_P64 && rhs_form == KH_RHS_FACTORED)
+    hipLaunchKernelGGL((k_rhs<double, KH_RHS_FACTORED>), grid, dim3(block), 0, strm, spin_chart, s, acc, n);
+  else if (precision == KH_P64)
+    hipLaunchKernelGGL((k_rhs<double, KH_RHS_PAPER>), grid, dim3(block), 0, strm, spin_chart, s, acc, n);
+  else if (rhs_form == KH_RHS_FACTORED)
+    hipLaunchKernelGGL((k_rhs<float, KH_RHS_FACTORED>), grid, dim3(block), 0, strm, spin_chart, s, acc, n);
+  else
+    hipLaunchKernelGGL((k_rhs<float, KH_RHS_PAPER>), grid, dim3(block), 0, strm, spin_chart, s, acc, n);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+kh_status kh_flops(int32_t method, int32_t rhs_form, kh_flop_counts* out) {
+  if (!out || (method != KH_RK4 && method != KH_DOPRI5) ||
+      (rhs_form != KH_RHS_FACTORED && rhs_form != KH_RHS_PAPER))
+    return KH_EINVAL;
+  Tally t_rhs, t_step;
+  const Cnt x[4] = {Cnt(0.0), Cnt(7.0), Cnt(-3.0), Cnt(2.0)};
+  const Cnt k[4] = {Cnt(1.2), Cnt(-0.6), Cnt(0.3), Cnt(-0.2)};
+  g_tally = &t_rhs;
+  if (rhs_form == KH_RHS_FACTORED)
+    (void)rhs<KH_RHS_FACTORED, Cnt>(Cnt(0.9), x, k);
+  else
+    (void)rhs<KH_RHS_PAPER, Cnt>(Cnt(0.9), x, k);
+  g_tally = &t_step;
+  Cnt xn[4], kn[4], a7[4], r, rd;
+  const Cnt a1[4] = {Cnt(0.01), Cnt(0.02), Cnt(-0.01), Cnt(0.005)};
+  int n_rhs;
+  if (method == KH_DOPRI5) {
+    if (rhs_form == KH_RHS_FACTORED)
+      (void)dp5_attempt<KH_RHS_FACTORED, Cnt, Cnt>(Cnt(0.9), x, k, a1, Cnt(0.1), Cnt(1e-8), Cnt(1e-8), xn, kn, a7, r,
+                                                   rd);
+    else
+      (void)dp5_attempt<KH_RHS_PAPER, Cnt, Cnt>(Cnt(0.9), x, k, a1, Cnt(0.1), Cnt(1e-8), Cnt(1e-8), xn, kn, a7, r, rd);
+    n_rhs = 6;
+  } else {
+    if (rhs_form == KH_RHS_FACTORED)
+      rk4_step<KH_RHS_FACTORED, Cnt, Cnt>(Cnt(0.9), x, k, a1, Cnt(0.1), xn, kn);
+    else
+      rk4_step<KH_RHS_PAPER, Cnt, Cnt>(Cnt(0.9), x, k, a1, Cnt(0.1), xn, kn);
+    n_rhs = 3;  // the fourth (first-stage) evaluation is counted by the caller
+  }
+  g_tally = nullptr;
+  out->add = t_rhs.add;
+  out->mul = t_rhs.mul;
+  out->div = t_rhs.div;
+  out->sqrt = t_rhs.sqrt;
+  out->step_add = t_step.add - n_rhs * t_rhs.add;
+  out->step_mul = t_step.mul - n_rhs * t_rhs.mul;
+  out->step_div = t_step.div - n_rhs * t_rhs.div;
+  out->step_sqrt = t_step.sqrt - n_rhs * t_rhs.sqrt;
+  return KH_OK;
+}
+
+}  // extern "C"

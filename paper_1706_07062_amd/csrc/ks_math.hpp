@@ -1,0 +1,264 @@
+// ks_math.hpp -- Cartesian Kerr-Schild geometry and the geodesic right-hand side.
+//
+// Everything here is a __host__ __device__ template on the scalar type T
+// (double, float, or the host-side operation counter), so the same source is
+// the device code and the operation count.
+//
+// Metric (Sec. 2.1, def:CKS): g_ab = eta_ab + f l_a l_b with
+//   f = 2 r^3 / (r^4 + a^2 z^2),
+//   l = (1, (r x + a y)/(r^2 + a^2), (r y - a x)/(r^2 + a^2), z / r),
+// and r the positive root of eq:CKSr, r^4 - (R^2 - a^2) r^2 - a^2 z^2 = 0.
+//
+// Right-hand side (Sec. 2.1, eq:opt0 / eq:opti): with xdot_{b,j} = g_{bc,j} k^c
+// (only spatial derivatives: the metric is stationary) and
+//   F = f (l^b k^j xdot_{b,j} - 1/2 l^j k^b xdot_{b,j}),  l^b = (-1, l_1, l_2, l_3),
+//   a^0 = k^j xdot_{0,j} - F,
+//   a^i = -k^j (xdot_{i,j} - 1/2 xdot_{j,i}) + F l_i.
+// Two evaluations of that formula are provided:
+//   * rhs_paper: forms the 12 values xdot_{b,j} and then the sums, as written;
+//   * rhs_factored (default): the same quantities regrouped further.  Because
+//     d_j g_bc = d_j f l_b l_c + f (d_j l_b l_c + l_b d_j l_c), one has
+//     xdot_{b,j} = l_b G_j + f K d_j l_b with K = l_c k^c and
+//     G_j = d_j f K + f k^c d_j l_c.  The Jacobian d_j l_i is a rank-one term
+//     plus a fixed 3x3 pattern, so the two contractions it enters become two
+//     dot products.  The null property l^b l_b = 0 and l_i d_j l_i = 0 (both
+//     follow from eq:CKSr) drop the first term of F.  The result equals
+//     rhs_paper up to rounding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace kh {
+
+// Scalar helpers dispatched on type.
+__host__ __device__ inline double ksqrt(double x) { return sqrt(x); }
+__host__ __device__ inline float ksqrt(float x) { return sqrtf(x); }
+
+template <typename T>
+struct Accel {
+  T a[4];  // d k^mu / d lambda
+  T r;     // Kerr-Schild radius at the point
+  T rdot;  // dr / dlambda = d_j r k^j
+};
+
+// Radius from eq:CKSr.  Both root formulas are exact; the second avoids
+// cancellation when R^2 < a^2.
+template <typename T>
+__host__ __device__ inline T ks_r2(T a2, T X, T Y, T Z) {
+  const T z2 = Z * Z;
+  const T w = X * X + Y * Y + z2 - a2;
+  const T q = ksqrt(w * w + T(4) * a2 * z2);
+  return (w >= T(0)) ? T(0.5) * (w + q) : T(2) * a2 * z2 / (q - w);
+}
+
+// The paper's regrouped form, written out with its 12 temporaries.
+template <typename T>
+__host__ __device__ inline Accel<T> rhs_paper(T a, const T x[4], const T k[4]) {
+  const T X = x[1], Y = x[2], Z = x[3];
+  const T a2 = a * a;
+  const T r2 = ks_r2(a2, X, Y, Z);
+  const T r = ksqrt(r2);
+  const T ir = T(1) / r;
+  const T iS = T(1) / (r2 + a2);
+  const T iD = T(1) / (r2 * r2 + a2 * Z * Z);
+  const T f = T(2) * r2 * r * iD;
+  const T l[4] = {T(1), (r * X + a * Y) * iS, (r * Y - a * X) * iS, Z * ir};
+  // d_j r = r (r^2 x_j + a^2 z delta_jz) / D
+  const T c = r * iD;
+  const T dr[3] = {c * r2 * X, c * r2 * Y, c * (r2 + a2) * Z};
+  // d_j f = f [3 d_j r / r - (4 r^3 d_j r + 2 a^2 z delta_jz) / D]
+  const T m = f * (T(3) * ir - T(4) * r2 * r * iD);
+  const T df[3] = {m * dr[0], m * dr[1], m * dr[2] - T(2) * f * a2 * Z * iD};
+  // dl[i][j] = d_j l_i (i = 1..3 stored at 0..2); d_j l_0 = 0.
+  const T px = (X - T(2) * r * l[1]) * iS;
+  const T py = (Y - T(2) * r * l[2]) * iS;
+  const T pz = -l[3] * ir;
+  const T rS = r * iS, aS = a * iS;
+  const T dl[3][3] = {{px * dr[0] + rS, px * dr[1] + aS, px * dr[2]},
+                      {py * dr[0] - aS, py * dr[1] + rS, py * dr[2]},
+                      {pz * dr[0], pz * dr[1], pz * dr[2] + ir}};
+  const T K = k[0] + l[1] * k[1] + l[2] * k[2] + l[3] * k[3];
+  T dK[3];
+  for (int j = 0; j < 3; ++j) dK[j] = k[1] * dl[0][j] + k[2] * dl[1][j] + k[3] * dl[2][j];
+  // xd[b][j] = xdot_{b,j} = (d_j f l_b + f d_j l_b) K + f l_b dK_j
+  T xd[4][3];
+  for (int j = 0; j < 3; ++j) xd[0][j] = df[j] * K + f * dK[j];
+  for (int b = 1; b < 4; ++b)
+    for (int j = 0; j < 3; ++j) xd[b][j] = (df[j] * l[b] + f * dl[b - 1][j]) * K + f * l[b] * dK[j];
+  // F = f (l^b k^j xd[b][j] - 1/2 l^j k^b xd[b][j])
+  T s1 = T(0), s2 = T(0);
+  for (int j = 0; j < 3; ++j) {
+    const T kj = k[j + 1];
+    s1 = s1 + kj * (-xd[0][j] + l[1] * xd[1][j] + l[2] * xd[2][j] + l[3] * xd[3][j]);
+    s2 = s2 + l[j + 1] * (k[0] * xd[0][j] + k[1] * xd[1][j] + k[2] * xd[2][j] + k[3] * xd[3][j]);
+  }
+  const T F = f * (s1 - T(0.5) * s2);
+  Accel<T> out;
+  out.a[0] = k[1] * xd[0][0] + k[2] * xd[0][1] + k[3] * xd[0][2] - F;
+  // the second sum runs over all four b (xdot_{0,i} is not zero), the first
+  // over spatial j only (xdot_{i,0} = 0)
+  for (int i = 1; i < 4; ++i) {
+    T s = T(0);
+    for (int j = 0; j < 3; ++j) s = s + k[j + 1] * xd[i][j];
+    T v = T(0);
+    for (int b = 0; b < 4; ++b) v = v + k[b] * xd[b][i - 1];
+    out.a[i] = -s + T(0.5) * v + F * l[i];
+  }
+  out.r = r;
+  out.rdot = dr[0] * k[1] + dr[1] * k[2] + dr[2] * k[3];
+  return out;
+}
+
+// Regrouped evaluation of the same right-hand side.
+template <typename T>
+__host__ __device__ inline Accel<T> rhs_factored(T a, const T x[4], const T k[4]) {
+  const T X = x[1], Y = x[2], Z = x[3];
+  const T k1 = k[1], k2 = k[2], k3 = k[3];
+  const T a2 = a * a;
+  const T r2 = ks_r2(a2, X, Y, Z);
+  const T r = ksqrt(r2);
+  const T ir = T(1) / r;
+  const T iS = T(1) / (r2 + a2);
+  const T iD = T(1) / (r2 * r2 + a2 * Z * Z);
+  const T f = T(2) * r2 * r * iD;
+  const T rS = r * iS, aS = a * iS;
+  const T l1 = rS * X + aS * Y, l2 = rS * Y - aS * X, l3 = Z * ir;
+  // gradient of r
+  const T c = r * iD;
+  const T cr2 = c * r2;
+  const T dr1 = cr2 * X, dr2 = cr2 * Y, dr3 = c * (r2 + a2) * Z;
+  const T rdot = dr1 * k1 + dr2 * k2 + dr3 * k3;
+  // gradient of f: m d_j r, minus 2 f a^2 z / D on the z component
+  const T m = f * (T(3) * ir - T(4) * r2 * r * iD);
+  // d_j l_i = p_i d_j r + B_ij with p = ((x - 2 r l1)/S, (y - 2 r l2)/S, -l3/r)
+  // and B = [[r/S, a/S, 0], [-a/S, r/S, 0], [0, 0, 1/r]].
+  const T px = (X - T(2) * r * l1) * iS;
+  const T py = (Y - T(2) * r * l2) * iS;
+  const T pz = -l3 * ir;
+  const T pk = px * k1 + py * k2 + pz * k3;
+  // P_i = k^j d_j l_i and dK_j = k^i d_j l_i
+  const T P1 = px * rdot + rS * k1 + aS * k2;
+  const T P2 = py * rdot - aS * k1 + rS * k2;
+  const T P3 = pz * rdot + ir * k3;
+  const T dK1 = dr1 * pk + rS * k1 - aS * k2;
+  const T dK2 = dr2 * pk + aS * k1 + rS * k2;
+  const T dK3 = dr3 * pk + ir * k3;
+  const T K = k[0] + l1 * k1 + l2 * k2 + l3 * k3;
+  // G_j = d_j f K + f dK_j
+  const T mK = m * K;
+  const T G1 = mK * dr1 + f * dK1;
+  const T G2 = mK * dr2 + f * dK2;
+  const T G3 = mK * dr3 - T(2) * f * a2 * Z * iD * K + f * dK3;
+  const T kG = k1 * G1 + k2 * G2 + k3 * G3;
+  // F = -1/2 f K l^j (G_j + f dK_j)
+  const T H1 = G1 + f * dK1, H2 = G2 + f * dK2, H3 = G3 + f * dK3;
+  const T F = T(-0.5) * f * K * (l1 * H1 + l2 * H2 + l3 * H3);
+  Accel<T> out;
+  out.a[0] = kG - F;
+  // a^i = -l_i kG - f K P_i + 1/2 K H_i + F l_i
+  const T fK = f * K, hK = T(0.5) * K, Fm = F - kG;
+  out.a[1] = Fm * l1 - fK * P1 + hK * H1;
+  out.a[2] = Fm * l2 - fK * P2 + hK * H2;
+  out.a[3] = Fm * l3 - fK * P3 + hK * H3;
+  out.r = r;
+  out.rdot = rdot;
+  return out;
+}
+
+template <int FORM, typename T>
+__host__ __device__ inline Accel<T> rhs(T a, const T x[4], const T k[4]) {
+  if constexpr (FORM == 1)
+    return rhs_paper<T>(a, x, k);
+  else
+    return rhs_factored<T>(a, x, k);
+}
+
+// Null condition: k^0 = [f L + sqrt(1 - f + f L^2)] / (1 - f), L = l_i k^i with
+// |k^i| = 1 scaled out: for general spatial k, the future root of
+// (f - 1) k0^2 + 2 f L k0 + |k|^2 + f L^2 = 0.
+__host__ __device__ inline double null_k0(double a, const double x[4], const double k[4], bool* ok) {
+  const double a2 = a * a;
+  const double r2 = ks_r2(a2, x[1], x[2], x[3]);
+  const double r = sqrt(r2);
+  const double iS = 1.0 / (r2 + a2);
+  const double f = 2.0 * r2 * r / (r2 * r2 + a2 * x[3] * x[3]);
+  const double l1 = (r * x[1] + a * x[2]) * iS, l2 = (r * x[2] - a * x[1]) * iS, l3 = x[3] / r;
+  const double L = l1 * k[1] + l2 * k[2] + l3 * k[3];
+  const double kk = k[1] * k[1] + k[2] * k[2] + k[3] * k[3];
+  const double disc = f * f * L * L + (1.0 - f) * (kk + f * L * L);
+  *ok = (f < 1.0) && (disc >= 0.0);
+  return (f * L + sqrt(disc)) / (1.0 - f);
+}
+
+// Time-like normalisation: with v = (1, v^i), u^0 = 1 / sqrt(1 - |v|^2 - f (1 + l.v)^2).
+__host__ __device__ inline double timelike_u0(double a, const double x[4], const double v[3], bool* ok) {
+  const double a2 = a * a;
+  const double r2 = ks_r2(a2, x[1], x[2], x[3]);
+  const double r = sqrt(r2);
+  const double iS = 1.0 / (r2 + a2);
+  const double f = 2.0 * r2 * r / (r2 * r2 + a2 * x[3] * x[3]);
+  const double l1 = (r * x[1] + a * x[2]) * iS, l2 = (r * x[2] - a * x[1]) * iS, l3 = x[3] / r;
+  const double lv = 1.0 + l1 * v[0] + l2 * v[1] + l3 * v[2];
+  const double nrm = 1.0 - (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - f * lv * lv;
+  *ok = nrm > 0.0;
+  return 1.0 / sqrt(nrm);
+}
+
+// Constants of motion in FP64: E = -k_0, L_z = x k_y - y k_x, Carter's Q and
+// mu^2 = -g k k, with covariant k_a = eta_ab k^b + f l_a (l.k).  Q uses the
+// spheroidal angle of the chart: cos(th) = z/r, sin(th) = rho / sqrt(r^2 + a^2),
+// p_th = cot(th)(x k_x + y k_y) - r sin(th) k_z,
+// Q = p_th^2 + cos^2(th) [a^2 (mu^2 - E^2) + L_z^2 / sin^2(th)].
+__host__ __device__ inline void constants(double a, const double x[4], const double k[4], double out[4]) {
+  const double a2 = a * a;
+  const double r2 = ks_r2(a2, x[1], x[2], x[3]);
+  const double r = sqrt(r2);
+  const double iS = 1.0 / (r2 + a2);
+  const double f = 2.0 * r2 * r / (r2 * r2 + a2 * x[3] * x[3]);
+  const double l1 = (r * x[1] + a * x[2]) * iS, l2 = (r * x[2] - a * x[1]) * iS, l3 = x[3] / r;
+  const double K = k[0] + l1 * k[1] + l2 * k[2] + l3 * k[3];
+  const double k0 = -k[0] + f * K, kx = k[1] + f * l1 * K, ky = k[2] + f * l2 * K, kz = k[3] + f * l3 * K;
+  const double E = -k0;
+  const double Lz = x[1] * ky - x[2] * kx;
+  const double mu2 = -(k0 * k[0] + kx * k[1] + ky * k[2] + kz * k[3]);
+  double rho = sqrt(x[1] * x[1] + x[2] * x[2]);
+  rho = rho < 1e-300 ? 1e-300 : rho;
+  const double cth = x[3] / r;
+  const double sth = rho * sqrt(iS);
+  const double pth = (cth / sth) * (x[1] * kx + x[2] * ky) - r * sth * kz;
+  out[0] = E;
+  out[1] = Lz;
+  out[2] = pth * pth + cth * cth * (a2 * (mu2 - E * E) + Lz * Lz / (sth * sth));
+  out[3] = mu2;
+}
+
+// Photon's xi = L_z / E in the physical frame (null rays run time-reversed in
+// the chart with spin -a: same E, opposite L_z).
+__host__ __device__ inline double photon_xi(double a_chart, const double x[4], const double k[4], bool reversed) {
+  const double a2 = a_chart * a_chart;
+  const double r2 = ks_r2(a2, x[1], x[2], x[3]);
+  const double r = sqrt(r2);
+  const double iS = 1.0 / (r2 + a2);
+  const double f = 2.0 * r2 * r / (r2 * r2 + a2 * x[3] * x[3]);
+  const double l1 = (r * x[1] + a_chart * x[2]) * iS, l2 = (r * x[2] - a_chart * x[1]) * iS, l3 = x[3] / r;
+  const double K = k[0] + l1 * k[1] + l2 * k[2] + l3 * k[3];
+  const double E = k[0] - f * K;
+  const double Lz = x[1] * (k[2] + f * l2 * K) - x[2] * (k[1] + f * l1 * K);
+  return reversed ? -Lz / E : Lz / E;
+}
+
+// Redshift nu_obs / nu_em for an emitter on the prograde Keplerian circular
+// orbit at radius r (spin a): Omega = 1/(r^{3/2} + a),
+// u^t = (r^{3/2} + a) / (r^{3/4} sqrt(r^{3/2} - 3 r^{1/2} + 2a)), g = 1/(u^t (1 - Omega xi)).
+// NaN inside the prograde photon orbit.
+__host__ __device__ inline double redshift(double r, double xi, double a) {
+  const double sr = sqrt(r);
+  const double r32 = r * sr;
+  const double den = r32 - 3.0 * sr + 2.0 * a;
+  if (!(den > 0.0)) return __builtin_nan("");
+  const double ut = (r32 + a) / (sr * sqrt(sr) * sqrt(den));  // r^{3/4} = r^{1/2} r^{1/4}
+  const double om = 1.0 / (r32 + a);
+  return 1.0 / (ut * (1.0 - om * xi));
+}
+
+}  // namespace kh

@@ -1,0 +1,235 @@
+// steppers.hpp -- Runge-Kutta steps for the second-order geodesic system.
+//
+// The state is (x^mu, k^mu) with x' = k and k' = acc(x, k).  Because x' is the
+// momentum itself, every stage of an explicit Runge-Kutta method can be formed
+// from the stage accelerations alone (Nystrom form): with the Butcher matrix A,
+//   K_i = k + h sum_l A_il acc_l,
+//   X_i = x + h c_i k + h^2 sum_l (A A)_il acc_l,
+// so a lane keeps 4 values per stage instead of 8.  This is the same method,
+// exactly, as the first-order form (c_i = sum_j A_ij holds for both tableaux).
+//
+// Tableaux: classic RK4 (the paper's default integrator, Sec. 3) and
+// Dormand & Prince (1980) 5(4) with first-same-as-last.  The combined
+// coefficients A A, b A and e A (e = b - b*) are folded at compile time.
+#pragma once
+
+#include "ks_math.hpp"
+
+namespace kh {
+
+// Scalar helpers for the norm, dispatched on type.
+__host__ __device__ inline double kabs(double x) { return fabs(x); }
+__host__ __device__ inline float kabs(float x) { return fabsf(x); }
+__host__ __device__ inline double kmax(double x, double y) { return x > y ? x : y; }
+__host__ __device__ inline float kmax(float x, float y) { return x > y ? x : y; }
+
+struct DP5Tab {
+  double c[7];
+  double A[7][7];
+  double b[7];
+  double e[7];      // b - b*
+  double AA[7][7];  // A A
+  double bA[7];     // b A
+  double eA[7];     // e A
+};
+
+constexpr DP5Tab make_dp5() {
+  DP5Tab t{};
+  const double A[7][7] = {
+      {0, 0, 0, 0, 0, 0, 0},
+      {1.0 / 5, 0, 0, 0, 0, 0, 0},
+      {3.0 / 40, 9.0 / 40, 0, 0, 0, 0, 0},
+      {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0, 0},
+      {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0, 0},
+      {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0, 0},
+      {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0}};
+  const double c[7] = {0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1, 1};
+  const double b[7] = {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0};
+  const double bs[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
+  for (int i = 0; i < 7; ++i) {
+    t.c[i] = c[i];
+    t.b[i] = b[i];
+    t.e[i] = b[i] - bs[i];
+    for (int j = 0; j < 7; ++j) t.A[i][j] = A[i][j];
+  }
+  for (int i = 0; i < 7; ++i)
+    for (int l = 0; l < 7; ++l) {
+      double s = 0;
+      for (int j = 0; j < 7; ++j) s += A[i][j] * A[j][l];
+      t.AA[i][l] = s;
+    }
+  for (int l = 0; l < 7; ++l) {
+    double sb = 0, se = 0;
+    for (int i = 0; i < 7; ++i) {
+      sb += b[i] * A[i][l];
+      se += (b[i] - bs[i]) * A[i][l];
+    }
+    t.bA[l] = sb;
+    t.eA[l] = se;
+  }
+  return t;
+}
+
+constexpr DP5Tab DP5 = make_dp5();
+
+template <typename TS, typename TR>
+struct Conv {
+  __host__ __device__ static TR to(TS v) { return static_cast<TR>(v); }
+  __host__ __device__ static TS from(TR v) { return static_cast<TS>(v); }
+};
+
+// One Dormand-Prince attempt from (x, k) with acceleration a1 = acc(x, k).
+// State and stage arithmetic in TS; right-hand side evaluated in TR.
+// Outputs the 5th-order state (xn, kn), its acceleration a7 (first stage of
+// the next step), the RMS error norm and the radius / radial rate at (xn, kn).
+template <int FORM, typename TS, typename TR>
+__host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], const TS a1[4], TS h, TS rtol,
+                                          TS atol, TS xn[4], TS kn[4], TS a7[4], TS& r_new, TS& rdot_new) {
+  TS S[6][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) S[0][c] = a1[c];
+  const TR ac = Conv<TS, TR>::to(a_c);
+#pragma unroll
+  for (int i = 1; i < 6; ++i) {
+    TR X[4], K[4];
+    X[0] = TR(0);  // the metric is stationary: t never enters the right-hand side
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      TS sx = TS(0), sk = TS(0);
+#pragma unroll
+      for (int l = 0; l < i; ++l) {
+        sx = sx + TS(DP5.AA[i][l]) * S[l][c];
+        sk = sk + TS(DP5.A[i][l]) * S[l][c];
+      }
+      if (c > 0) X[c] = Conv<TS, TR>::to(x[c] + h * (TS(DP5.c[i]) * k[c] + h * sx));
+      K[c] = Conv<TS, TR>::to(k[c] + h * sk);
+    }
+    const Accel<TR> ra = rhs<FORM, TR>(ac, X, K);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) S[i][c] = Conv<TS, TR>::from(ra.a[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    TS sx = TS(0), sk = TS(0);
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+      sx = sx + TS(DP5.bA[l]) * S[l][c];
+      sk = sk + TS(DP5.b[l]) * S[l][c];
+    }
+    xn[c] = x[c] + h * (k[c] + h * sx);
+    kn[c] = k[c] + h * sk;
+  }
+  {
+    TR X[4], K[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      X[c] = Conv<TS, TR>::to(xn[c]);
+      K[c] = Conv<TS, TR>::to(kn[c]);
+    }
+    const Accel<TR> ra = rhs<FORM, TR>(ac, X, K);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a7[c] = Conv<TS, TR>::from(ra.a[c]);
+    r_new = Conv<TS, TR>::from(ra.r);
+    rdot_new = Conv<TS, TR>::from(ra.rdot);
+  }
+  TS s2 = TS(0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    TS ex = TS(0), ek = TS(DP5.e[6]) * a7[c];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+      ex = ex + TS(DP5.eA[l]) * S[l][c];
+      ek = ek + TS(DP5.e[l]) * S[l][c];
+    }
+    ex = h * h * ex;
+    ek = h * ek;
+    const TS sx = atol + rtol * kmax(kabs(x[c]), kabs(xn[c]));
+    const TS sk = atol + rtol * kmax(kabs(k[c]), kabs(kn[c]));
+    const TS qx = ex / sx, qk = ek / sk;
+    s2 = s2 + qx * qx + qk * qk;
+  }
+  return ksqrt(s2 * TS(0.125));
+}
+
+// One classic RK4 step of length h from (x, k) with acceleration a1 = acc(x, k).
+template <int FORM, typename TS, typename TR>
+__host__ __device__ inline void rk4_step(TS a_c, const TS x[4], const TS k[4], const TS a1[4], TS h, TS xn[4],
+                                         TS kn[4]) {
+  const TR ac = Conv<TS, TR>::to(a_c);
+  const TS hh = TS(0.5) * h;
+  TR X[4], K[4];
+  TS a2[4], a3[4], a4[4];
+  X[0] = TR(0);
+#pragma unroll
+  for (int c = 1; c < 4; ++c) X[c] = Conv<TS, TR>::to(x[c] + hh * k[c]);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) K[c] = Conv<TS, TR>::to(k[c] + hh * a1[c]);
+  {
+    const Accel<TR> ra = rhs<FORM, TR>(ac, X, K);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a2[c] = Conv<TS, TR>::from(ra.a[c]);
+  }
+#pragma unroll
+  for (int c = 1; c < 4; ++c) X[c] = Conv<TS, TR>::to(x[c] + hh * (k[c] + hh * a1[c]));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) K[c] = Conv<TS, TR>::to(k[c] + hh * a2[c]);
+  {
+    const Accel<TR> ra = rhs<FORM, TR>(ac, X, K);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a3[c] = Conv<TS, TR>::from(ra.a[c]);
+  }
+#pragma unroll
+  for (int c = 1; c < 4; ++c) X[c] = Conv<TS, TR>::to(x[c] + h * (k[c] + hh * a2[c]));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) K[c] = Conv<TS, TR>::to(k[c] + h * a3[c]);
+  {
+    const Accel<TR> ra = rhs<FORM, TR>(ac, X, K);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a4[c] = Conv<TS, TR>::from(ra.a[c]);
+  }
+  const TS h6 = h / TS(6);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    xn[c] = x[c] + h * (k[c] + h6 * (a1[c] + a2[c] + a3[c]));
+    kn[c] = k[c] + h6 * (a1[c] + TS(2) * (a2[c] + a3[c]) + a4[c]);
+  }
+}
+
+// Cubic Hermite interpolant on theta in [0, 1] over a step of length h.
+__host__ __device__ inline double herm(double th, double y0, double m0, double y1, double m1, double h) {
+  const double t2 = th * th, t3 = t2 * th;
+  return (2 * t3 - 3 * t2 + 1) * y0 + (t3 - 2 * t2 + th) * h * m0 + (-2 * t3 + 3 * t2) * y1 + (t3 - t2) * h * m1;
+}
+__host__ __device__ inline double dherm(double th, double y0, double m0, double y1, double m1, double h) {
+  const double t2 = th * th;
+  return (6 * t2 - 6 * th) * y0 + (3 * t2 - 4 * th + 1) * h * m0 + (-6 * t2 + 6 * th) * y1 +
+         (3 * t2 - 2 * th) * h * m1;
+}
+
+// Zero of the Hermite interpolant of (y0 - target .. y1 - target) in [0, 1]
+// given a sign change or an exact zero at the end: Newton from the linear
+// guess, with bisection whenever an iterate leaves the current bracket.
+__host__ __device__ inline double hermite_zero(double y0, double m0, double y1, double m1, double h) {
+  if (y1 == 0.0) return 1.0;
+  double lo = 0.0, hi = 1.0;
+  double th = y0 / (y0 - y1);
+  for (int it = 0; it < 60; ++it) {
+    const double p = herm(th, y0, m0, y1, m1, h);
+    if (p == 0.0) break;
+    if ((p < 0.0) == (y0 < 0.0))
+      lo = th;
+    else
+      hi = th;
+    const double dp = dherm(th, y0, m0, y1, m1, h);
+    double tn = th - p / dp;
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    if (fabs(tn - th) <= 1e-15) {
+      th = tn;
+      break;
+    }
+    th = tn;
+  }
+  return th;
+}
+
+}  // namespace kh

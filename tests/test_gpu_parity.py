@@ -1,0 +1,317 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Positions must agree to 1e-6 relative with identical
+statuses on every ray the oracle does not flag as ill-conditioned
+(tests/parity_util.py states the policy)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1706_07062_amd as K
+from paper_1706_07062_amd import workloads as W
+from parity_util import (POS_TOL, compare, gpu_image, kcam, oracle_image, oracle_params, rel_pos)
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch.cuda.set_device(0)
+    c = K.Context(0)
+    yield c
+    c.close()
+
+
+def _random_states(n, a, seed):
+    """Random points outside the horizon with null momenta (oracle's metric)."""
+    rng = np.random.default_rng(seed)
+    ys = []
+    while len(ys) < n:
+        x = rng.uniform(-1, 1, 3) * rng.choice([3.0, 15.0, 300.0])
+        r = O.radius(a, *x)
+        if not (1.05 * (1 + np.sqrt(1 - a * a)) < r < 500):
+            continue
+        k = rng.normal(size=3)
+        y = np.array([0.0, *x, 0.0, *k])
+        g, _ = O.metric(a, y[:4])
+        A, B, Cq = g[0, 0], g[0, 1:] @ k, k @ g[1:, 1:] @ k
+        if A >= 0:
+            continue
+        y[4] = (B + np.sqrt(B * B - A * Cq)) / (-A)
+        ys.append(y)
+    return np.array(ys).T.copy()
+
+
+@pytest.mark.parametrize("form", [K.RHS_FACTORED, K.RHS_PAPER])
+def test_rhs_point_parity(ctx, form):
+    """The right-hand side (metric, derivatives, eq:opt0/opti) at 3001 random
+    points (a ragged multiple of the block) equals the oracle's Christoffel form."""
+    say(f"rhs point parity form={form}")
+    for a in (0.0, -0.99):
+        s = _random_states(3001, a, seed=11 + form)
+        spin = torch.full((s.shape[1],), a, dtype=torch.float64, device="cuda")
+        acc = ctx.kh_rhs(K.P64, form, spin, torch.from_numpy(s).cuda()).cpu().numpy()
+        for i in range(0, s.shape[1], 7):
+            want = O.rhs(a, s[:4, i], s[4:, i])
+            assert np.abs(acc[:, i] - want).max() <= 2e-12 * np.abs(want).max(), i
+        acc32 = ctx.kh_rhs(K.P32, form, spin, torch.from_numpy(s).cuda()).cpu().numpy()
+        for i in range(0, s.shape[1], 31):
+            want = O.rhs(a, s[:4, i], s[4:, i])
+            assert np.abs(acc32[:, i] - want).max() <= 5e-4 * np.abs(want).max(), i
+
+
+def test_init_rays_matches_oracle(ctx):
+    """Image-plane initial data of several concatenated cameras (ragged sizes)."""
+    say("init rays")
+    cams = [W.Camera(0.99, 1000.0, 17.0, -12, 12, -12, 12, 37, 29), W.Camera(0.0, 500.0, 85.0, -5, 7, -3, 9, 64, 3),
+            W.Camera(-0.5, 1000.0, 60.0, -12, 12, -12, 12, 1, 1)]
+    n = sum(c.n for c in cams)
+    st = K.State(n, k_cross=2)
+    ctx.kh_init_rays([kcam(c) for c in cams], st)
+    g = st.numpy()
+    off = 0
+    for c in cams:
+        o = O.camera_rays(c.a, c.r_obs, c.incl, c.alpha_min, c.alpha_max, c.beta_min, c.beta_max, c.width,
+                          c.height)
+        np.testing.assert_allclose(g["s"][:, off:off + c.n], o["s"], rtol=1e-14, atol=1e-13)
+        assert np.all(g["status"][off:off + c.n] == K.ACTIVE)
+        assert np.all(g["kind"][off:off + c.n] == K.NULL)
+        assert np.all(g["spin"][off:off + c.n] == c.a)
+        off += c.n
+    assert np.all(np.isnan(g["cross"]))
+    # constants at init: null norm of order 1e-16
+    assert np.abs(g["c0"][3]).max() < 1e-14
+
+
+def test_init_list_and_timelike_match_oracle(ctx):
+    say("init list + timelike")
+    rw = W.surrogate_rays(1000)
+    st = K.State(1000)
+    t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()  # noqa: E731
+    ctx.kh_init_rays_list(t(rw["a"]), t(rw["incl"]), t(rw["alpha"]), t(rw["beta"]), 1000.0, st)
+    o = O.list_rays(rw["a"], rw["incl"], rw["alpha"], rw["beta"], 1000.0)
+    np.testing.assert_allclose(st.s.cpu().numpy(), o["s"], rtol=1e-14, atol=1e-13)
+    pw = W.particles(777)
+    st = K.State(777)
+    ctx.kh_init_geodesics(K.TIMELIKE, t(pw["a"]), t(pw["x3"]), t(pw["v3"]), st)
+    o = O.timelike(pw["a"], pw["x3"], pw["v3"])
+    np.testing.assert_allclose(st.s.cpu().numpy(), o["s"], rtol=1e-13, atol=1e-13)
+    assert np.array_equal(st.status.cpu().numpy(), o["status"])
+    assert np.abs(st.c0.cpu().numpy()[3] - 1.0).max() < 1e-12  # mu^2 = 1
+
+
+def test_schwarzschild_64_rk4_parity(ctx):
+    """a = 0, 64x64 at 60 deg, fixed-step RK4 h = 0.01 r: full image."""
+    say("schwarzschild 64x64 RK4")
+    cam = W.schwarzschild_64()
+    p = K.kh_default_params(method=K.RK4, h_coeff=0.01, r_escape=1000.0)
+    st = gpu_image(ctx, [cam], p)
+    g = st.numpy()
+    o = oracle_image(cam, oracle_params(p))
+    rep = compare(g, o)
+    say(f"  {rep}")
+    assert rep["status_mismatch"] == 0 and rep["n_pos_bad"] == 0
+    assert rep["ill"] < 0.01 * rep["n"]
+    assert np.array_equal(g["n_acc"][~o["ill"]], o["n_acc"][~o["ill"]])
+    assert set(np.unique(g["status"])) <= {K.CAPTURED, K.ESCAPED}
+
+
+@pytest.mark.parametrize("incl", [17.0, 60.0])
+def test_kerr_ragged_image_dopri5_parity(ctx, incl):
+    """a = 0.99, 100x77 image (several blocks plus a ragged tail), DOPRI5
+    rtol 1e-8, four crossing slots: full element-wise comparison."""
+    say(f"kerr 100x77 DOPRI5 incl={incl}")
+    cam = W.Camera(0.99, 1000.0, incl, -12, 12, -12, 12, 100, 77)
+    p = K.kh_default_params(k_cross=4)
+    st = gpu_image(ctx, [cam], p, k_cross=4)
+    g = st.numpy()
+    o = oracle_image(cam, oracle_params(p))
+    rep = compare(g, o)
+    say(f"  {rep}")
+    well = ~o["ill"]
+    assert rep["status_mismatch"] == 0 and rep["n_pos_bad"] == 0
+    assert rep["ill"] < 0.01 * rep["n"]
+    assert rep["max_rel_t"] < POS_TOL and rep["max_rel_k"] < 1e-5
+    # crossings: same count, same (r, phi, g)
+    assert np.array_equal(g["n_cross"][well], o["n_cross"][well])
+    gc, oc = g["cross"][well], o["cross"][well]
+    both = ~np.isnan(oc)
+    assert np.array_equal(np.isnan(gc), np.isnan(oc))
+    assert np.max(np.abs(gc[both] - oc[both]) / np.maximum(np.abs(oc[both]), 1.0)) < POS_TOL
+    # constants of motion conserved to the tolerance
+    d = np.abs(g["c1"][:3] - g["c0"][:3]) / np.maximum(np.abs(g["c0"][:3]), 1.0)
+    assert np.max(d[:, well]) < 1e-6
+
+
+def test_kerr_1024_both_inclinations_sampled(ctx):
+    """The full workload (a = 0.99, 1024x1024 at 17 and 60 deg in one launch, the
+    benchmark's launch configuration), checked on 600 pixels of each image."""
+    say("kerr 2x1024^2 sampled")
+    cams = W.kerr_1024()
+    p = K.kh_default_params(k_cross=4)
+    st = gpu_image(ctx, cams, p, k_cross=4)
+    g = st.numpy()
+    stats = ctx.kh_stats(st)
+    assert sum(stats["status_counts"]) == 2 * 1024 * 1024
+    assert stats["status_counts"][K.ACTIVE] == 0 and stats["status_counts"][K.MAX_STEPS] == 0
+    assert stats["n_acc"] == int(g["n_acc"].astype(np.int64).sum())
+    for j, cam in enumerate(cams):
+        pix = W.strided_pixels(cam.n, 600, offset=j * 17)
+        o = oracle_image(cam, oracle_params(p), pix=pix)
+        rep = compare(g, o, idx=pix + j * cam.n)
+        say(f"  incl={cam.incl_deg}: {rep}")
+        assert rep["status_mismatch"] == 0 and rep["n_pos_bad"] == 0
+        assert rep["ill"] < 0.02 * rep["n"]
+        well = ~o["ill"]
+        assert np.array_equal(g["n_cross"][pix + j * cam.n][well], o["n_cross"][well])
+
+
+def reduced_precision_errors(g, o, idx):
+    """Step-independent errors of a reduced-precision run against FP64: status,
+    first equatorial crossing (r, g; interpolated at z = 0, so independent of
+    where the steps fall) and the escape direction k^i/|k|.  Final positions
+    are not comparable: an escaping ray stops anywhere within its last step
+    (up to 0.1 r), and different step sequences stop at different places."""
+    gs, gst = g["s"][:, idx], g["status"][idx]
+    agree = float(np.mean(gst == o["status"]))
+    both = (g["n_cross"][idx] > 0) & (o["n_cross"] > 0)
+    cr = np.abs(g["cross"][idx, 0, 0] - o["cross"][:, 0, 0])[both] / o["cross"][both, 0, 0]
+    okg = both & ~np.isnan(o["cross"][:, 0, 2])
+    cg = np.abs(g["cross"][idx, 0, 2] - o["cross"][:, 0, 2])[okg] / o["cross"][okg, 0, 2]
+    esc = (gst == K.ESCAPED) & (o["status"] == K.ESCAPED)
+    ug = gs[5:8, esc] / np.linalg.norm(gs[5:8, esc], axis=0)
+    uo = o["s"][5:8, esc] / np.linalg.norm(o["s"][5:8, esc], axis=0)
+    ang = np.arccos(np.clip(np.sum(ug * uo, axis=0), -1, 1))
+    return dict(status_agree=agree, cross_r_median=float(np.median(cr)), cross_r_p99=float(np.quantile(cr, 0.99)),
+                cross_g_median=float(np.median(cg)), escape_angle_median=float(np.median(ang)),
+                escape_angle_p99=float(np.quantile(ang, 0.99)))
+
+
+@pytest.mark.parametrize("prec", [K.P32, K.PMIXED])
+def test_reduced_precision_error_reported(ctx, prec):
+    """FP32 and mixed FP32/FP64 runs of a 128x128 a = 0.99 image against the
+    FP64 oracle.  These errors are reported quantities (parity unpinned); the
+    bounds only guard against gross breakage."""
+    say(f"reduced precision {prec}")
+    cam = W.kerr_image(60.0, side=128)
+    tol = 1e-6 if prec == K.P32 else 1e-8
+    p = K.kh_default_params(precision=prec, k_cross=4, rtol=tol, atol=tol)
+    st = gpu_image(ctx, [cam], p, k_cross=4)
+    g = st.numpy()
+    pix = W.strided_pixels(cam.n, 800)
+    o = oracle_image(cam, oracle_params(K.kh_default_params(k_cross=4)), pix=pix, conditioning=False)
+    rep = reduced_precision_errors(g, o, pix)
+    say(f"  {rep}")
+    assert rep["status_agree"] > 0.97
+    assert rep["cross_r_median"] < (1e-3 if prec == K.P32 else 1e-5)
+    assert rep["escape_angle_median"] < (1e-3 if prec == K.P32 else 1e-5)
+
+
+def test_resume_is_bitwise(ctx):
+    """Pausing every ray after 17 accepted steps and resuming gives exactly the
+    uninterrupted result (FP64), and MAX_STEPS is reported in between."""
+    say("resume bitwise")
+    cam = W.kerr_image(60.0, side=48)
+    p = K.kh_default_params(k_cross=4)
+    ref = gpu_image(ctx, [cam], p, k_cross=4).numpy()
+    st = K.State(cam.n, k_cross=4)
+    ctx.kh_init_rays([kcam(cam)], st)
+    p17 = K.kh_default_params(k_cross=4, max_steps=17)
+    ctx.kh_integrate(p17, st)
+    torch.cuda.synchronize()
+    mid = st.status.cpu().numpy()
+    assert np.all(mid == K.MAX_STEPS) or np.mean(mid == K.MAX_STEPS) > 0.9
+    for _ in range(200):
+        ctx.kh_integrate(p17, st)
+        if ctx.kh_stats(st)["status_counts"][K.MAX_STEPS] == 0:
+            break
+    g = st.numpy()
+    for name in ("s", "status", "n_acc", "n_rej", "lam", "phi", "n_cross"):
+        assert np.array_equal(g[name], ref[name]), name
+    assert np.array_equal(np.nan_to_num(g["cross"], nan=-7.0), np.nan_to_num(ref["cross"], nan=-7.0))
+
+
+def test_launch_shape_does_not_change_results(ctx):
+    """Each lane's arithmetic is independent of scheduling: block size, grid size
+    and refill threshold give bitwise identical FP64 results."""
+    say("launch shape determinism")
+    cam = W.kerr_image(17.0, side=64)
+    base = gpu_image(ctx, [cam], K.kh_default_params(k_cross=4), k_cross=4).numpy()
+    for bs, gb, rf in ((64, 0, 1), (128, 7, 64), (256, 1, 16), (192, 3, 5)):
+        g = gpu_image(ctx, [cam], K.kh_default_params(k_cross=4, block_size=bs, grid_blocks=gb, refill_min=rf),
+                      k_cross=4).numpy()
+        assert np.array_equal(g["s"], base["s"]), (bs, gb, rf)
+        assert np.array_equal(g["n_acc"], base["n_acc"])
+
+
+def test_particles_to_t_end_parity(ctx):
+    """Time-like geodesics of the particle workload (a strided sample of 256 of
+    its 2^20 draws), DOPRI5 rtol 1e-8 to t = 1e4 M with exact landing."""
+    say("particles t_end")
+    pw = W.particles()
+    idx = np.arange(0, 1 << 20, 4099)[:256]
+    a, x3, v3 = pw["a"][idx], pw["x3"][:, idx].copy(), pw["v3"][:, idx].copy()
+    t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()  # noqa: E731
+    st = K.State(len(idx))
+    ctx.kh_init_geodesics(K.TIMELIKE, t(a), t(x3), t(v3), st)
+    p = K.kh_default_params(t_end=1e4, r_escape=1e4)
+    ctx.kh_integrate(p, st)
+    g = st.numpy()
+    o = O.integrate(O.timelike(a, x3, v3), oracle_params(p))
+    assert np.array_equal(g["status"], o["status"])
+    assert np.all(g["status"] == K.T_END)
+    assert np.abs(g["s"][0] - 1e4).max() <= 1e-12 * 1e4
+    d = rel_pos(g["s"], o["s"])
+    say(f"  max rel pos {d.max():.2e}, median {np.median(d):.2e}")
+    assert d.max() < 1e-6
+    drift = np.abs(g["c1"] - g["c0"]) / np.maximum(np.abs(g["c0"]), 1.0)
+    say(f"  drift max E {drift[0].max():.2e} Lz {drift[1].max():.2e} Q {drift[2].max():.2e} mu2 {drift[3].max():.2e}")
+    assert drift.max() < 1e-5
+
+
+def test_failure_statuses_forced_from_the_host(ctx):
+    """Planted NaN state -> FAILED; max_steps = 1 -> MAX_STEPS; rays already
+    terminal are left untouched."""
+    say("failure statuses")
+    cam = W.kerr_image(60.0, side=8)
+    st = K.State(cam.n)
+    ctx.kh_init_rays([kcam(cam)], st)
+    st.s[1, 3] = float("nan")
+    st.status[5] = K.CAPTURED
+    before5 = st.s[:, 5].clone()
+    ctx.kh_integrate(K.kh_default_params(max_steps=1), st)
+    g = st.numpy()
+    assert g["status"][3] == K.FAILED
+    assert g["status"][5] == K.CAPTURED and torch.equal(st.s[:, 5], before5)
+    others = np.setdiff1d(np.arange(cam.n), [3, 5])
+    assert np.all(g["status"][others] == K.MAX_STEPS)
+    assert np.all(g["n_acc"][others] == 1)
+
+
+def test_argument_errors(ctx):
+    say("argument errors")
+    st = K.State(16)
+    bad = K.kh_default_params(rtol=-1.0)
+    with pytest.raises(K.KerrHipError, match="rtol"):
+        ctx.kh_integrate(bad, st)
+    with pytest.raises(K.KerrHipError, match="k_cross"):
+        ctx.kh_integrate(K.kh_default_params(k_cross=4), st)
+    with pytest.raises(K.KerrHipError):
+        ctx.kh_integrate(K.kh_default_params(method=K.RK4, t_end=5.0), st)
+    cam = W.Camera(1.5, 1000.0, 60.0, -1, 1, -1, 1, 4, 4)
+    with pytest.raises(K.KerrHipError, match="camera"):
+        ctx.kh_init_rays([kcam(cam)], st)
+    cam = W.Camera(0.5, 1000.0, 60.0, -1, 1, -1, 1, 4, 3)
+    with pytest.raises(K.KerrHipError, match="state.n"):
+        ctx.kh_init_rays([kcam(cam)], st)
+    # a host pointer is refused before any launch
+    host = torch.zeros(16, dtype=torch.float64)
+    saved = st.c.h
+    st.c.h = host.data_ptr()
+    with pytest.raises(K.KerrHipError, match="device memory"):
+        ctx.kh_integrate(K.kh_default_params(), st)
+    st.c.h = saved
