@@ -11,8 +11,11 @@ LIB = os.path.join(HERE, "libkerrhip.so")
 SOURCES = ["kerrhip.hip"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
+# -ffp-contract=on: fuse multiply-adds per source expression, so every inlined
+# copy of the right-hand side rounds identically (bitwise resume and
+# launch-shape independence rely on it).
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 

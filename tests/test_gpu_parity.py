@@ -230,6 +230,7 @@ def test_resume_is_bitwise(ctx):
         if ctx.kh_stats(st)["status_counts"][K.MAX_STEPS] == 0:
             break
     g = st.numpy()
+    say(f"  max |resumed - uninterrupted| / |x|: {np.max(rel_pos(g['s'], ref['s'])):.3e}")
     for name in ("s", "status", "n_acc", "n_rej", "lam", "phi", "n_cross"):
         assert np.array_equal(g[name], ref[name]), name
     assert np.array_equal(np.nan_to_num(g["cross"], nan=-7.0), np.nan_to_num(ref["cross"], nan=-7.0))
@@ -263,8 +264,10 @@ def test_particles_to_t_end_parity(ctx):
     g = st.numpy()
     o = O.integrate(O.timelike(a, x3, v3), oracle_params(p))
     assert np.array_equal(g["status"], o["status"])
-    assert np.all(g["status"] == K.T_END)
-    assert np.abs(g["s"][0] - 1e4).max() <= 1e-12 * 1e4
+    # a few low-energy draws near r0 = 6 plunge; every other particle lands on t_end
+    landed = g["status"] == K.T_END
+    assert landed.mean() > 0.95 and np.all(np.isin(g["status"], [K.T_END, K.CAPTURED]))
+    assert np.abs(g["s"][0, landed] - 1e4).max() <= 1e-12 * 1e4
     d = rel_pos(g["s"], o["s"])
     say(f"  max rel pos {d.max():.2e}, median {np.median(d):.2e}")
     assert d.max() < 1e-6
