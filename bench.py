@@ -29,6 +29,24 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1706_07062_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# HBM bytes per launch of the FP64 DOPRI5 kernel from the committed rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs (profiles/k_integrate_dopri5_fp64_kerr1024.md),
+# valid only for the kernel source they were taken on.
+PROFILED_TRAFFIC = {"source_hash": "70883a54c93a95bb", "bytes": (343502.0625 * 2.0 + 500538.59375 * 1.0) * 1024}
+
+
 def algorithmic_flops(K, stats, n_rays, method, form):
     """Operation count of one integrate launch: per DOPRI5 attempt 6 right-hand
     sides plus the stage combinations and error norm; one extra right-hand side
@@ -109,7 +127,10 @@ def run_gpu(args):
         rejected_steps_per_ray=stats["n_rej"] / n,
         integrate_kernel_ms=float(np.mean(kern_ms)),
         roofline=dict(bound="alu", achieved=tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                      frac=tflops / FP64_PEAK_TFLOPS, traffic=None,
+                      frac=tflops / FP64_PEAK_TFLOPS,
+                      traffic=(PROFILED_TRAFFIC["bytes"] if kernel_source_hash() == PROFILED_TRAFFIC["source_hash"]
+                               else None),
+                      traffic_unit="bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
                       flops_per_launch=flops, flop_per_rhs=rhs_f, flop_per_attempt_overhead=step_f),
     )
     if not args.no_extras:
@@ -167,6 +188,21 @@ def extras(args, ctx, K, W, torch):
     return res
 
 
+def copy_probe(mib):
+    """A plain device-to-device copy of known size (reads and writes `mib` MiB),
+    run before the workload so a counter-collection run sees a reference for
+    the HBM-byte counters."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy probe: 3 copies of {mib} MiB")
+
+
 def cpu_baseline(args):
     """The oracle on a bounded sample of the same workload: strided pixels of
     both images, all host threads."""
@@ -198,11 +234,14 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, help="MiB; plain copy before the run (counter reference)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the integrator shards by ray range with no exchange on the hot "
               "path, and this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
     out, _ = run_gpu(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args)

@@ -88,7 +88,7 @@ typedef struct {
   int32_t *kind;    /* [n]: KH_NULL or KH_TIMELIKE */
   double *h;        /* [n]: next DOPRI5 step (<= 0: choose h0); resume data */
   double *lam;      /* [n]: affine parameter reached */
-  double *phi;      /* [n]: unwrapped Cartesian azimuth atan2(y, x), summed per step */
+  double *phi;      /* [n]: unwrapped Cartesian azimuth atan2(y, x) (kept up to date when crossings are recorded) */
   int32_t *status;  /* [n]: KH_ACTIVE ... KH_FAILED */
   int32_t *n_acc;   /* [n]: accepted steps, cumulative over calls */
   int32_t *n_rej;   /* [n]: rejected DOPRI5 attempts, cumulative */
@@ -115,10 +115,11 @@ typedef struct {
   double t_end;      /* > 0: stop and land on x^0 = t_end (DOPRI5 only) */
   double r_fp64;     /* KH_PMIXED: FP64 right-hand side when any lane of the wave has r < r_fp64 */
   int64_t max_steps; /* accepted steps per call before KH_MAX_STEPS (> 0) */
-  int32_t block_size;   /* threads per block, multiple of 64 in [64, 1024]; 0 = 256 */
+  int32_t block_size;   /* threads per block: 64, 128, 192 or 256; 0 = 256 */
   int32_t grid_blocks;  /* persistent grid size; 0 = fill the device from the occupancy query */
-  int32_t refill_min;   /* a wave refills once at least this many lanes are idle (1..64); 0 = 16 */
-  int32_t reserved;
+  int32_t refill_min;   /* a wave refills once at least this many lanes are idle (1..64); 0 = 4 */
+  int32_t waves_per_eu; /* register budget of the kernel variant: 0 or 1 = compiler's choice; DOPRI5 with
+                           the factored form also has 3 and 4 (FP64 / mixed) and 4 and 5 (FP32) */
 } kh_params;
 /* scale(r) = r for null geodesics and r^{3/2} for time-like ones.  DOPRI5
  * controller: accept if err <= 1 (err = RMS over the 8 components of

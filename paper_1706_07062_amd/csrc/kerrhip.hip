@@ -134,8 +134,10 @@ __device__ inline int64_t wave_grab(unsigned long long idle, unsigned long long*
 // METHOD: KH_RK4 / KH_DOPRI5.  PREC: KH_P64 / KH_P32 / KH_PMIXED.
 // FORM: right-hand-side evaluation (KH_RHS_FACTORED / KH_RHS_PAPER).
 // ---------------------------------------------------------------------------
-template <int METHOD, int PREC, int FORM>
-__global__ void __launch_bounds__(256) k_integrate(KParams P, KState S, unsigned long long* qctr) {
+// WPE: minimum waves per SIMD the register allocation must allow (1 = no limit).
+template <int METHOD, int PREC, int FORM, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_integrate(KParams P, KState S, unsigned long long* qctr) {
   using TS = typename std::conditional<PREC == KH_P32, float, double>::type;  // state / stages
   using TF = typename std::conditional<PREC == KH_P64, double, float>::type;  // fast right-hand side
 
@@ -147,8 +149,12 @@ __global__ void __launch_bounds__(256) k_integrate(KParams P, KState S, unsigned
   TS x[4], k[4], a1[4];
   TS r_cur = TS(0), rdot_cur = TS(0);
   TS a_c = TS(0);
-  double a_phys = 0.0, h = 0.0, lam = 0.0, phi = 0.0;
+  double a_phys = 0.0, h = 0.0, lam = 0.0, rcap = 0.0;
   int kind = 0, nacc = 0, nrej = 0, ncross = 0, status = KH_ACTIVE;
+  // Unwrapped azimuth = atan2(y, x) + 2 pi * wind: wind counts passages across
+  // the negative x axis, so no arctangent is needed on ordinary steps.
+  int wind = 0;
+  double phi_in = 0.0;
   int64_t steps = 0, tries = 0;
   bool after_reject = false;
 
@@ -171,7 +177,9 @@ __global__ void __launch_bounds__(256) k_integrate(KParams P, KState S, unsigned
           a_c = (TS)(kind == KH_NULL ? -a_phys : a_phys);
           h = S.h[id];
           lam = S.lam[id];
-          phi = S.phi[id];
+          phi_in = S.phi[id];
+          wind = (int)rint((phi_in - atan2((double)x[2], (double)x[1])) * (0.5 / M_PI));
+          rcap = P.r_h_factor * r_horizon((double)a_c);
           nacc = S.n_acc[id];
           nrej = S.n_rej[id];
           ncross = S.n_cross ? S.n_cross[id] : 0;
@@ -212,7 +220,7 @@ __global__ void __launch_bounds__(256) k_integrate(KParams P, KState S, unsigned
         for (int c = 0; c < 4; ++c) bad = bad || (x[c] != x[c]) || (k[c] != k[c]);
         if (bad)
           status = KH_FAILED;
-        else if ((double)r_cur < P.r_h_factor * r_horizon((double)a_c))
+        else if ((double)r_cur < rcap)
           status = KH_CAPTURED;
         else if ((double)r_cur > P.r_escape && rdot_cur > TS(0))
           status = KH_ESCAPED;
@@ -262,9 +270,11 @@ __global__ void __launch_bounds__(256) k_integrate(KParams P, KState S, unsigned
             // Unwrapped azimuth and equatorial crossings between the two nodes.
             const double x0 = x[1], y0 = x[2], z0 = x[3];
             const double x1 = xn[1], y1 = xn[2], z1 = xn[3];
-            const double phi0 = phi;
-            phi = phi0 + atan2(x0 * y1 - y0 * x1, x0 * x1 + y0 * y1);
+            const int wind0 = wind;
+            const double cr = x0 * y1 - y0 * x1;
+            wind += (y0 >= 0.0 && y1 < 0.0 && cr > 0.0) - (y0 < 0.0 && y1 >= 0.0 && cr < 0.0);
             if ((z0 < 0.0 && z1 > 0.0) || (z0 > 0.0 && z1 < 0.0) || (z1 == 0.0 && z0 != 0.0)) {
+              const double phi0 = atan2(y0, x0) + (2.0 * M_PI) * wind0;
               const double th = hermite_zero(z0, (double)k[3], z1, (double)kn[3], h);
               const double xc = herm(th, x0, (double)k[1], x1, (double)kn[1], h);
               const double yc = herm(th, y0, (double)k[2], y1, (double)kn[2], h);
@@ -289,7 +299,7 @@ __global__ void __launch_bounds__(256) k_integrate(KParams P, KState S, unsigned
               ++ncross;
             }
           }
-          if ((double)r_new < P.r_h_factor * r_horizon((double)a_c))
+          if ((double)r_new < rcap)
             status = KH_CAPTURED;
           else if ((double)r_new > P.r_escape && rdot_new > TS(0))
             status = KH_ESCAPED;
@@ -347,7 +357,7 @@ __global__ void __launch_bounds__(256) k_integrate(KParams P, KState S, unsigned
       }
       S.h[ray] = h;
       S.lam[ray] = lam;
-      S.phi[ray] = phi;
+      S.phi[ray] = (P.k_cross > 0) ? atan2((double)x[2], (double)x[1]) + (2.0 * M_PI) * wind : phi_in;
       S.status[ray] = status;
       S.n_acc[ray] = nacc;
       S.n_rej[ray] = nrej;
@@ -538,6 +548,14 @@ inline Cnt ksqrt(Cnt x) {
   ++g_tally->sqrt;
   return Cnt(std::sqrt(x.v));
 }
+inline Cnt krsqrt(Cnt x) {
+  ++g_tally->sqrt;
+  return Cnt(1.0 / std::sqrt(x.v));
+}
+inline Cnt krcp(Cnt x) {
+  ++g_tally->div;
+  return Cnt(1.0 / x.v);
+}
 inline Cnt kabs(Cnt x) { return Cnt(std::fabs(x.v)); }
 inline Cnt kmax(Cnt x, Cnt y) { return x.v > y.v ? x : y; }
 
@@ -619,24 +637,33 @@ kh_status set_device(kh_ctx* ctx) {
   return KH_OK;
 }
 
-template <int M, int P, int F>
+template <int M, int P, int F, int W>
 void* kernel_ptr() {
-  return reinterpret_cast<void*>(&k_integrate<M, P, F>);
+  return reinterpret_cast<void*>(&k_integrate<M, P, F, W>);
 }
 
-void* pick_kernel(int method, int prec, int form) {
-#define KH_PICK(M, P, F) \
-  if (method == M && prec == P && form == F) return kernel_ptr<M, P, F>();
-  KH_PICK(KH_RK4, KH_P64, KH_RHS_FACTORED)
-  KH_PICK(KH_RK4, KH_P32, KH_RHS_FACTORED)
-  KH_PICK(KH_RK4, KH_PMIXED, KH_RHS_FACTORED)
-  KH_PICK(KH_RK4, KH_P64, KH_RHS_PAPER)
-  KH_PICK(KH_RK4, KH_P32, KH_RHS_PAPER)
-  KH_PICK(KH_DOPRI5, KH_P64, KH_RHS_FACTORED)
-  KH_PICK(KH_DOPRI5, KH_P32, KH_RHS_FACTORED)
-  KH_PICK(KH_DOPRI5, KH_PMIXED, KH_RHS_FACTORED)
-  KH_PICK(KH_DOPRI5, KH_P64, KH_RHS_PAPER)
-  KH_PICK(KH_DOPRI5, KH_P32, KH_RHS_PAPER)
+// Kernel variants: every method / precision / form at the default register
+// budget, plus DOPRI5 with the factored right-hand side at 2, 3 and 4 waves per
+// SIMD for the occupancy choice.
+void* pick_kernel(int method, int prec, int form, int wpe) {
+#define KH_PICK(M, P, F, W) \
+  if (method == M && prec == P && form == F && wpe == W) return kernel_ptr<M, P, F, W>();
+  KH_PICK(KH_RK4, KH_P64, KH_RHS_FACTORED, 1)
+  KH_PICK(KH_RK4, KH_P32, KH_RHS_FACTORED, 1)
+  KH_PICK(KH_RK4, KH_PMIXED, KH_RHS_FACTORED, 1)
+  KH_PICK(KH_RK4, KH_P64, KH_RHS_PAPER, 1)
+  KH_PICK(KH_RK4, KH_P32, KH_RHS_PAPER, 1)
+  KH_PICK(KH_DOPRI5, KH_P64, KH_RHS_FACTORED, 1)
+  KH_PICK(KH_DOPRI5, KH_P32, KH_RHS_FACTORED, 1)
+  KH_PICK(KH_DOPRI5, KH_PMIXED, KH_RHS_FACTORED, 1)
+  KH_PICK(KH_DOPRI5, KH_P64, KH_RHS_PAPER, 1)
+  KH_PICK(KH_DOPRI5, KH_P32, KH_RHS_PAPER, 1)
+  KH_PICK(KH_DOPRI5, KH_P64, KH_RHS_FACTORED, 3)
+  KH_PICK(KH_DOPRI5, KH_P64, KH_RHS_FACTORED, 4)
+  KH_PICK(KH_DOPRI5, KH_P32, KH_RHS_FACTORED, 4)
+  KH_PICK(KH_DOPRI5, KH_P32, KH_RHS_FACTORED, 5)
+  KH_PICK(KH_DOPRI5, KH_PMIXED, KH_RHS_FACTORED, 3)
+  KH_PICK(KH_DOPRI5, KH_PMIXED, KH_RHS_FACTORED, 4)
 #undef KH_PICK
   return nullptr;
 }
@@ -816,9 +843,10 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
     return fail(ctx, KH_EUNSUPPORTED, "the paper-form right-hand side is built for P64 and P32 only");
   const int block = p->block_size ? p->block_size : 256;
   if (block < 64 || block > 256 || block % 64) return fail(ctx, KH_EINVAL, "block_size must be 64, 128, 192 or 256");
-  const int refill = p->refill_min ? p->refill_min : 16;
+  const int refill = p->refill_min ? p->refill_min : 4;
   if (refill < 1 || refill > 64) return fail(ctx, KH_EINVAL, "refill_min must be in [1, 64]");
   if (p->grid_blocks < 0) return fail(ctx, KH_EINVAL, "grid_blocks must be >= 0");
+  if (p->waves_per_eu < 0 || p->waves_per_eu > 8) return fail(ctx, KH_EINVAL, "waves_per_eu must be in [0, 8]");
   kh_status s = check_state(ctx, st, p->k_cross > 0);
   if (s != KH_OK) return s;
   if (p->k_cross > st->k_cross) return fail(ctx, KH_EINVAL, "params.k_cross exceeds state.k_cross");
@@ -841,8 +869,8 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   kp.k_cross = p->k_cross;
   kp.refill_min = refill;
 
-  void* fn = pick_kernel(p->method, p->precision, p->rhs_form);
-  if (!fn) return fail(ctx, KH_EUNSUPPORTED, "no kernel for this method / precision / rhs_form");
+  void* fn = pick_kernel(p->method, p->precision, p->rhs_form, p->waves_per_eu ? p->waves_per_eu : 1);
+  if (!fn) return fail(ctx, KH_EUNSUPPORTED, "no kernel for this method / precision / rhs_form / waves_per_eu");
   int grid = p->grid_blocks;
   if (grid == 0) {
     int per_cu = 0;

@@ -30,9 +30,52 @@
 
 namespace kh {
 
-// Scalar helpers dispatched on type.
-__host__ __device__ inline double ksqrt(double x) { return sqrt(x); }
-__host__ __device__ inline float ksqrt(float x) { return sqrtf(x); }
+// Reciprocal and reciprocal square root.  On the device: the hardware
+// estimate (v_rcp / v_rsq) refined by Newton-Raphson iterations; for FP64 two
+// iterations take the ~2^-23 relative estimate to about one ulp (each
+// iteration squares the relative error): r <- r + r (1 - x r) and
+// y <- y + y (1/2 - x y^2 / 2).  FP32 estimates are already within one ulp.
+// On the host (operation counts, CPU checks) plain IEEE operations.
+__host__ __device__ inline double krcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+__host__ __device__ inline float krcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+__host__ __device__ inline double krsqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  double e = fma(-hx, y * y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-hx, y * y, 0.5);
+  return fma(y, e, y);
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+__host__ __device__ inline float krsqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rsqf(x);
+#else
+  return 1.0f / sqrtf(x);
+#endif
+}
+// sqrt(x) = x / sqrt(x) for x > 0 (0 stays 0).
+__host__ __device__ inline double ksqrt(double x) { return x > 0.0 ? x * krsqrt(x) : x; }
+__host__ __device__ inline float ksqrt(float x) { return x > 0.0f ? x * krsqrt(x) : x; }
 
 template <typename T>
 struct Accel {
@@ -48,7 +91,8 @@ __host__ __device__ inline T ks_r2(T a2, T X, T Y, T Z) {
   const T z2 = Z * Z;
   const T w = X * X + Y * Y + z2 - a2;
   const T q = ksqrt(w * w + T(4) * a2 * z2);
-  return (w >= T(0)) ? T(0.5) * (w + q) : T(2) * a2 * z2 / (q - w);
+  if (w >= T(0)) return T(0.5) * (w + q);
+  return T(2) * a2 * z2 * krcp(q - w);  // only inside r < a
 }
 
 // The paper's regrouped form, written out with its 12 temporaries.
@@ -57,10 +101,11 @@ __host__ __device__ inline Accel<T> rhs_paper(T a, const T x[4], const T k[4]) {
   const T X = x[1], Y = x[2], Z = x[3];
   const T a2 = a * a;
   const T r2 = ks_r2(a2, X, Y, Z);
-  const T r = ksqrt(r2);
-  const T ir = T(1) / r;
-  const T iS = T(1) / (r2 + a2);
-  const T iD = T(1) / (r2 * r2 + a2 * Z * Z);
+  const T ir = krsqrt(r2);
+  const T r = r2 * ir;
+  const T S = r2 + a2, D = r2 * r2 + a2 * Z * Z;
+  const T iSD = krcp(S * D);
+  const T iS = D * iSD, iD = S * iSD;
   const T f = T(2) * r2 * r * iD;
   const T l[4] = {T(1), (r * X + a * Y) * iS, (r * Y - a * X) * iS, Z * ir};
   // d_j r = r (r^2 x_j + a^2 z delta_jz) / D
@@ -116,10 +161,12 @@ __host__ __device__ inline Accel<T> rhs_factored(T a, const T x[4], const T k[4]
   const T k1 = k[1], k2 = k[2], k3 = k[3];
   const T a2 = a * a;
   const T r2 = ks_r2(a2, X, Y, Z);
-  const T r = ksqrt(r2);
-  const T ir = T(1) / r;
-  const T iS = T(1) / (r2 + a2);
-  const T iD = T(1) / (r2 * r2 + a2 * Z * Z);
+  // one reciprocal square root gives r and 1/r; one reciprocal gives 1/S and 1/D
+  const T ir = krsqrt(r2);
+  const T r = r2 * ir;
+  const T S = r2 + a2, D = r2 * r2 + a2 * Z * Z;
+  const T iSD = krcp(S * D);
+  const T iS = D * iSD, iD = S * iSD;
   const T f = T(2) * r2 * r * iD;
   const T rS = r * iS, aS = a * iS;
   const T l1 = rS * X + aS * Y, l2 = rS * Y - aS * X, l3 = Z * ir;

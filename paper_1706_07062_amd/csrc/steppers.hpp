@@ -145,7 +145,7 @@ __host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], 
     ek = h * ek;
     const TS sx = atol + rtol * kmax(kabs(x[c]), kabs(xn[c]));
     const TS sk = atol + rtol * kmax(kabs(k[c]), kabs(kn[c]));
-    const TS qx = ex / sx, qk = ek / sk;
+    const TS qx = ex * krcp(sx), qk = ek * krcp(sk);
     s2 = s2 + qx * qx + qk * qk;
   }
   return ksqrt(s2 * TS(0.125));
