@@ -148,7 +148,12 @@ void kh_default_params(kh_params *p);
  * in camera order: the rays of camera c occupy ids [off_c, off_c + w_c h_c).
  * Requires st->n == sum of width*height.  Writes s, spin, kind (KH_NULL),
  * h = 0, lam = 0, phi = atan2(y, x), status, n_acc = n_rej = 0, n_cross = 0,
- * cross = NaN and c0. */
+ * cross = NaN and c0.  The camera table is copied to the context (one small
+ * host-to-device copy on `stream`).  cams == NULL reuses the table of the last
+ * call on this context (same n_cams): then the call is one kernel launch and
+ * may be captured into a HIP graph; a captured launch reads the context's table
+ * when the graph is replayed, so upload no other table on that context while
+ * the graph is in use. */
 kh_status kh_init_rays(kh_ctx *ctx, const kh_camera *cams, int32_t n_cams, kh_state *st, void *stream);
 
 /* Rays with individual parameters (device arrays [n]): physical spin, inclination,
@@ -178,6 +183,10 @@ kh_status kh_read_state(kh_ctx *ctx, const kh_state *st, int64_t first, int64_t 
 /* Reduce the state on the device: out[0..5] = count per status, out[6] = sum of
  * n_acc, out[7] = sum of n_rej.  Synchronises the stream. */
 kh_status kh_stats(kh_ctx *ctx, const kh_state *st, int64_t out[8], void *stream);
+
+/* Same reduction as kh_stats, asynchronously into caller device memory
+ * d_out [8] (int64); no host synchronisation, so it may be captured in a graph. */
+kh_status kh_stats_device(kh_ctx *ctx, const kh_state *st, int64_t *d_out, void *stream);
 
 /* Evaluate the right-hand side (the 4 accelerations d k^mu / d lambda) at n
  * points: spin_chart [n] is the chart spin, s [8][n] the states, acc [4][n]

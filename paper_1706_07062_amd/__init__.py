@@ -52,7 +52,7 @@ class kh_flop_counts(C.Structure):
 
 
 EXPORTS = ["kh_create", "kh_destroy", "kh_last_error", "kh_default_params", "kh_init_rays", "kh_init_rays_list",
-           "kh_init_geodesics", "kh_integrate", "kh_read_state", "kh_stats", "kh_rhs", "kh_flops"]
+           "kh_init_geodesics", "kh_integrate", "kh_read_state", "kh_stats", "kh_stats_device", "kh_rhs", "kh_flops"]
 
 _lib = None
 
@@ -79,6 +79,7 @@ def lib():
         L.kh_integrate.argtypes = [vp, P(kh_params), P(kh_state), vp]
         L.kh_read_state.argtypes = [vp, P(kh_state), i64, i64, vp, vp, vp]
         L.kh_stats.argtypes = [vp, P(kh_state), P(i64), vp]
+        L.kh_stats_device.argtypes = [vp, P(kh_state), vp, vp]
         L.kh_rhs.argtypes = [vp, i32, i32, vp, vp, vp, i64, vp]
         L.kh_flops.argtypes = [i32, i32, P(kh_flop_counts)]
         for name in EXPORTS:
@@ -145,9 +146,21 @@ class Context:
             msg = lib().kh_last_error(self.handle)
             raise KerrHipError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
 
-    def kh_init_rays(self, cams, st: "State", stream=None):
+    def kh_init_rays(self, cams, st: "State", stream=None, n_cams=None):
+        """cams: list of kh_camera, or None to reuse the table of the last call
+        (then pass n_cams; this form is a single kernel launch)."""
+        if cams is None:
+            self._check(lib().kh_init_rays(self.handle, None, n_cams, C.byref(st.c), _stream(stream)),
+                        "kh_init_rays")
+            return
         arr = (kh_camera * len(cams))(*cams)
         self._check(lib().kh_init_rays(self.handle, arr, len(cams), C.byref(st.c), _stream(stream)), "kh_init_rays")
+
+    def kh_stats_device(self, st: "State", out, stream=None):
+        if out.dtype != torch.int64 or not out.is_cuda or out.numel() < 8:
+            raise ValueError("out must be an int64 CUDA tensor with 8 elements")
+        self._check(lib().kh_stats_device(self.handle, C.byref(st.c), out.data_ptr(), _stream(stream)),
+                    "kh_stats_device")
 
     def kh_init_rays_list(self, spin, incl, alpha, beta, r_obs, st: "State", stream=None):
         for t in (spin, incl, alpha, beta):

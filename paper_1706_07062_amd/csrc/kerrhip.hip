@@ -31,7 +31,8 @@ static_assert(sizeof(kh_state) == 120, "kh_state layout");
 
 namespace {
 
-constexpr int kQueueSlots = 4;  // work-queue counters per context
+constexpr int kQueueSlots = 16;  // work-queue counters per context
+constexpr int kParts = 8;        // ray-range partitions = XCDs of an MI355X
 
 struct KState {
   int64_t n;
@@ -113,20 +114,36 @@ __global__ void k_reset_counters(unsigned long long* q, int n) {
   if (threadIdx.x < n) q[threadIdx.x] = 0ull;
 }
 
-// Grab up to popcount(idle) consecutive ray ids for the idle lanes of this
-// wave.  Returns the lane's new id, or -1.  Wave-uniform call.
-__device__ inline int64_t wave_grab(unsigned long long idle, unsigned long long* qctr, int64_t n, bool& exhausted) {
+// Work stealing over kParts contiguous partitions of the ray range.  A wave
+// starts on the partition of its XCD (workgroups are dispatched round-robin
+// over the XCDs, so blockIdx.x % kParts), which keeps a refill's neighbouring
+// ids in that XCD's L2, and moves on to the next partition when its own is
+// drained.  One atomic per refill; lane offsets from mbcnt over the ballot of
+// idle lanes.  Wave-uniform call; `cursor` counts partitions already drained
+// by this wave (kParts = all work handed out).  Returns the lane's new id or -1.
+__device__ inline int64_t wave_grab(unsigned long long idle, unsigned long long* qctr, int64_t n, int home,
+                                    int& cursor) {
   const int cnt = __popcll(idle);
   const int leader = __ffsll((long long)idle) - 1;
   const int lane = __lane_id();
-  unsigned long long base = 0;
-  if (lane == leader) base = atomicAdd(qctr, (unsigned long long)cnt);
-  base = __shfl(base, leader);
-  if (base + (unsigned long long)cnt >= (unsigned long long)n) exhausted = true;
-  if (!((idle >> lane) & 1ull)) return -1;
-  const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(idle >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)idle, 0u));
-  const unsigned long long id = base + rank;
-  return id < (unsigned long long)n ? (int64_t)id : -1;
+  const unsigned rank =
+      __builtin_amdgcn_mbcnt_hi((unsigned)(idle >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)idle, 0u));
+  while (cursor < kParts) {
+    const int p = (home + cursor) % kParts;
+    const int64_t lo = n * p / kParts, hi = n * (p + 1) / kParts;
+    const unsigned long long size = (unsigned long long)(hi - lo);
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(qctr + p, (unsigned long long)cnt);
+    base = __shfl(base, leader);
+    if (base < size) {
+      if (base + (unsigned long long)cnt >= size) ++cursor;  // this grab drains the partition
+      if (!((idle >> lane) & 1ull)) return -1;
+      const unsigned long long off = base + rank;
+      return off < size ? lo + (int64_t)off : -1;
+    }
+    ++cursor;
+  }
+  return -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -143,7 +160,8 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
 
   const int64_t n = S.n;
   int64_t ray = -1;
-  bool exhausted = false;
+  const int home = blockIdx.x % kParts;
+  int cursor = 0;  // partitions this wave has seen drained (wave-uniform)
   bool fresh = false;
 
   TS x[4], k[4], a1[4];
@@ -161,8 +179,8 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
   while (true) {
     // ---- refill idle lanes (wave-uniform decision) ----
     const unsigned long long idle = __ballot(ray < 0);
-    if (!exhausted && idle != 0ull && (__popcll(idle) >= P.refill_min || idle == ~0ull)) {
-      const int64_t id = wave_grab(idle, qctr, n, exhausted);
+    if (cursor < kParts && idle != 0ull && (__popcll(idle) >= P.refill_min || idle == ~0ull)) {
+      const int64_t id = wave_grab(idle, qctr, n, home, cursor);
       if (ray < 0 && id >= 0) {
         const int st = S.status[id];
         if (st == KH_ACTIVE || st == KH_MAX_STEPS) {
@@ -192,7 +210,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
       }
     }
     if (__ballot(ray >= 0) == 0ull) {
-      if (exhausted) break;
+      if (cursor >= kParts) break;
       continue;
     }
     if (ray < 0) continue;
@@ -572,6 +590,8 @@ struct kh_ctx {
   kh_camera* d_cams = nullptr;
   int64_t* d_offs = nullptr;
   int cam_cap = 0;
+  int cams_uploaded = 0;        // cameras currently in d_cams / d_offs
+  int64_t cams_total = 0;       // their total pixel count
   kh_camera* h_cams = nullptr;  // pinned staging
   int64_t* h_offs = nullptr;
   hipEvent_t cam_evt = nullptr;
@@ -609,23 +629,39 @@ bool is_device_ptr(const void* p) {
   return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
+// True while `stream` is being captured into a graph: runtime queries such as
+// hipPointerGetAttributes are then skipped (the arrays were checked when the
+// same state was used eagerly; alignment and NULL checks still apply).
+bool capturing(void* stream) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs == hipStreamCaptureStatusActive;
+}
+
+thread_local bool g_skip_ptr_query = false;
+
+bool device_ok(const void* p) { return g_skip_ptr_query ? p != nullptr : is_device_ptr(p); }
+
 kh_status check_state(kh_ctx* ctx, const kh_state* st, bool need_cross) {
   if (!st) return fail(ctx, KH_EINVAL, "state is NULL");
   if (st->n < 1 || st->n >= (int64_t(1) << 31)) return fail(ctx, KH_EINVAL, "state.n must be in [1, 2^31)");
   if (st->k_cross < 0 || st->k_cross > 8) return fail(ctx, KH_EINVAL, "state.k_cross must be in [0, 8]");
   const void* d8[] = {st->s, st->spin, st->h, st->lam, st->phi};
   for (const void* p : d8)
-    if (!p || !aligned(p, 8) || !is_device_ptr(p))
+    if (!p || !aligned(p, 8) || !device_ok(p))
       return fail(ctx, KH_EINVAL, "state arrays s, spin, h, lam, phi must be 8-byte aligned device memory");
   const void* d4[] = {st->kind, st->status, st->n_acc, st->n_rej};
   for (const void* p : d4)
-    if (!p || !aligned(p, 4) || !is_device_ptr(p))
+    if (!p || !aligned(p, 4) || !device_ok(p))
       return fail(ctx, KH_EINVAL, "state arrays kind, status, n_acc, n_rej must be 4-byte aligned device memory");
   const void* opt8[] = {st->c0, st->c1, st->cross};
   for (const void* p : opt8)
-    if (p && (!aligned(p, 8) || !is_device_ptr(p)))
+    if (p && (!aligned(p, 8) || !device_ok(p)))
       return fail(ctx, KH_EINVAL, "state arrays c0, c1, cross must be NULL or 8-byte aligned device memory");
-  if (st->n_cross && (!aligned(st->n_cross, 4) || !is_device_ptr(st->n_cross)))
+  if (st->n_cross && (!aligned(st->n_cross, 4) || !device_ok(st->n_cross)))
     return fail(ctx, KH_EINVAL, "state.n_cross must be NULL or 4-byte aligned device memory");
   if (need_cross && st->k_cross > 0 && (!st->cross || !st->n_cross))
     return fail(ctx, KH_EINVAL, "state.k_cross > 0 requires cross and n_cross");
@@ -728,7 +764,24 @@ const char* kh_last_error(const kh_ctx* c) { return c ? c->err.c_str() : "NULL c
 
 kh_status kh_init_rays(kh_ctx* ctx, const kh_camera* cams, int32_t n_cams, kh_state* st, void* stream) {
   if (!ctx) return KH_EINVAL;
-  if (!cams || n_cams < 1) return fail(ctx, KH_EINVAL, "need at least one camera");
+  g_skip_ptr_query = capturing(stream);
+  if (n_cams < 1) return fail(ctx, KH_EINVAL, "need at least one camera");
+  if (!cams) {
+    // Reuse the table uploaded by an earlier call: a single kernel launch, so
+    // this form can be captured into a graph.
+    if (n_cams != ctx->cams_uploaded) return fail(ctx, KH_EINVAL, "cams == NULL needs the same n_cams as the last upload");
+    kh_status s = check_state(ctx, st, false);
+    if (s != KH_OK) return s;
+    if (st->n != ctx->cams_total) return fail(ctx, KH_EINVAL, "state.n must equal the total pixel count of the cameras");
+    if ((s = set_device(ctx)) != KH_OK) return s;
+    const KState ks = to_k(st);
+    const int block = 256;
+    const int64_t grid = (st->n + block - 1) / block;
+    hipLaunchKernelGGL(k_init_rays, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)stream, ctx->d_cams,
+                       ctx->d_offs, n_cams, ks);
+    KH_HIP(ctx, hipGetLastError());
+    return KH_OK;
+  }
   int64_t total = 0;
   for (int i = 0; i < n_cams; ++i) {
     const kh_camera& c = cams[i];
@@ -775,6 +828,8 @@ kh_status kh_init_rays(kh_ctx* ctx, const kh_camera* cams, int32_t n_cams, kh_st
   KH_HIP(ctx,
          hipMemcpyAsync(ctx->d_offs, ctx->h_offs, (n_cams + 1) * sizeof(int64_t), hipMemcpyHostToDevice, strm));
   KH_HIP(ctx, hipEventRecord(ctx->cam_evt, strm));
+  ctx->cams_uploaded = n_cams;
+  ctx->cams_total = total;
   const KState ks = to_k(st);
   const int block = 256;
   const int64_t grid = (st->n + block - 1) / block;
@@ -786,6 +841,7 @@ kh_status kh_init_rays(kh_ctx* ctx, const kh_camera* cams, int32_t n_cams, kh_st
 kh_status kh_init_rays_list(kh_ctx* ctx, const double* spin, const double* incl, const double* alpha,
                             const double* beta, double r_obs, kh_state* st, void* stream) {
   if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = false;
   kh_status s = check_state(ctx, st, false);
   if (s != KH_OK) return s;
   const double* ins[] = {spin, incl, alpha, beta};
@@ -806,6 +862,7 @@ kh_status kh_init_rays_list(kh_ctx* ctx, const double* spin, const double* incl,
 kh_status kh_init_geodesics(kh_ctx* ctx, int32_t kind, const double* spin, const double* x3, const double* v3,
                             kh_state* st, void* stream) {
   if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = false;
   if (kind != KH_NULL && kind != KH_TIMELIKE) return fail(ctx, KH_EINVAL, "kind must be KH_NULL or KH_TIMELIKE");
   kh_status s = check_state(ctx, st, false);
   if (s != KH_OK) return s;
@@ -825,6 +882,7 @@ kh_status kh_init_geodesics(kh_ctx* ctx, int32_t kind, const double* spin, const
 
 kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stream) {
   if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = capturing(stream);
   if (!p) return fail(ctx, KH_EINVAL, "params is NULL");
   if (p->method != KH_RK4 && p->method != KH_DOPRI5) return fail(ctx, KH_EINVAL, "unknown method");
   if (p->precision != KH_P64 && p->precision != KH_P32 && p->precision != KH_PMIXED)
@@ -881,7 +939,7 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   if (grid > need) grid = (int)need;
   hipStream_t strm = (hipStream_t)stream;
   unsigned long long* q = ctx->d_queue;
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, strm, q, 1);
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, strm, q, kParts);
   KH_HIP(ctx, hipGetLastError());
   const KState ks = to_k(st);
   void* args[] = {(void*)&kp, (void*)&ks, (void*)&q};
@@ -892,6 +950,7 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
 kh_status kh_read_state(kh_ctx* ctx, const kh_state* st, int64_t first, int64_t count, double* host_s,
                         int32_t* host_status, void* stream) {
   if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = false;
   kh_status s = check_state(ctx, st, false);
   if (s != KH_OK) return s;
   if (first < 0 || count < 0 || first + count > st->n) return fail(ctx, KH_EINVAL, "range outside the state");
@@ -915,6 +974,7 @@ kh_status kh_read_state(kh_ctx* ctx, const kh_state* st, int64_t first, int64_t 
 
 kh_status kh_stats(kh_ctx* ctx, const kh_state* st, int64_t out[8], void* stream) {
   if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = false;
   if (!out) return fail(ctx, KH_EINVAL, "out is NULL");
   kh_status s = check_state(ctx, st, false);
   if (s != KH_OK) return s;
@@ -930,6 +990,25 @@ kh_status kh_stats(kh_ctx* ctx, const kh_state* st, int64_t out[8], void* stream
   KH_HIP(ctx, hipMemcpyAsync(h, ctx->d_stats, sizeof h, hipMemcpyDeviceToHost, strm));
   KH_HIP(ctx, hipStreamSynchronize(strm));
   for (int i = 0; i < 8; ++i) out[i] = (int64_t)h[i];
+  return KH_OK;
+}
+
+kh_status kh_stats_device(kh_ctx* ctx, const kh_state* st, int64_t* d_out, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = capturing(stream);
+  if (!d_out || !aligned(d_out, 8) || !device_ok(d_out))
+    return fail(ctx, KH_EINVAL, "d_out must be 8-byte aligned device memory for 8 counts");
+  kh_status s = check_state(ctx, st, false);
+  if (s != KH_OK) return s;
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  hipStream_t strm = (hipStream_t)stream;
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(d_out);
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, strm, out, 8);
+  const int block = 256;
+  int64_t grid = std::min<int64_t>((st->n + block - 1) / block, 4 * std::max(ctx->n_cu, 1));
+  hipLaunchKernelGGL(k_stats, dim3((unsigned)grid), dim3(block), 0, strm, st->status, st->n_acc, st->n_rej, st->n,
+                     out);
+  KH_HIP(ctx, hipGetLastError());
   return KH_OK;
 }
 
