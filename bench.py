@@ -185,7 +185,81 @@ def extras(args, ctx, K, W, torch):
         res[name] = dict(ns_per_step_per_ray=dt * 1e9 / s["n_acc"], steps=s["n_acc"], kernel_ms=dt * 1e3,
                          workload="a=0.999, 1024x1024, r_obs=1024, 60 deg, h=0.01r")
         log(f"{name}: {res[name]['ns_per_step_per_ray']:.4f} ns per RK4 step per ray")
+    res["batched_256_images"] = batched_extra(ctx, K, W, torch)
+    res["particles_2p20"] = particles_extra(ctx, K, W, torch)
     return res
+
+
+def batched_extra(ctx, K, W, torch):
+    """256 images of uneven size (32^2 .. 1024^2, spins and inclinations drawn)
+    in one persistent, autotuned, graph-captured launch, MIXED precision at
+    rtol 1e-6; against one launch per image."""
+    from paper_1706_07062_amd.batched import BatchedImages, camera_struct
+
+    cams = W.batched_images()
+    p = K.kh_default_params(precision=K.PMIXED, rtol=1e-6, atol=1e-6)
+    b = BatchedImages(ctx, cams, p, constants=False, tune=True, log=None)
+    b.capture()
+    times = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.replay()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    st = b.stats()
+    n = b.n
+    # one launch per image (eager), same precision and default launch shape
+    states = [K.State(c.n, constants=False) for c in cams]
+    kc = [camera_struct(c) for c in cams]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, s in zip(kc, states):
+        ctx.kh_init_rays([c], s)
+        ctx.kh_integrate(p, s)
+    torch.cuda.synchronize()
+    t_per = time.perf_counter() - t0
+    del states
+    out = dict(rays=n, images=len(cams), graph_replay_s=min(times), rays_per_s=n / min(times),
+               per_image_launches_s=t_per, per_image_rays_per_s=n / t_per,
+               accepted_steps_per_ray=st["n_acc"] / n, tuned_launch=b.choice, precision="mixed", rtol=1e-6)
+    log(f"batched: {n} rays in {min(times):.3f} s (graph, one launch) vs {t_per:.3f} s (per-image launches)")
+    return out
+
+
+def particles_extra(ctx, K, W, torch):
+    """2^20 time-like geodesics to t = 1e4 M: FP64 (rtol 1e-8) and FP32
+    (rtol 1e-6), constants-of-motion drift per particle."""
+    pw = W.particles()
+    n = len(pw["a"])
+    t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()  # noqa: E731
+    spin, x3, v3 = t(pw["a"]), t(pw["x3"]), t(pw["v3"])
+    out = {}
+    finals = {}
+    for name, prec, tol in (("fp64", K.P64, 1e-8), ("fp32", K.P32, 1e-6)):
+        st = K.State(n)
+        p = K.kh_default_params(precision=prec, rtol=tol, atol=tol, t_end=1e4, r_escape=1e4)
+        ctx.kh_init_geodesics(K.TIMELIKE, spin, x3, v3, st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.kh_integrate(p, st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s = ctx.kh_stats(st)
+        c0, c1 = st.c0.cpu().numpy(), st.c1.cpu().numpy()
+        landed = st.status.cpu().numpy() == K.T_END
+        drift = (np.abs(c1 - c0) / np.maximum(np.abs(c0), 1.0))[:, landed]
+        out[name] = dict(seconds=dt, particles_per_s=n / dt, steps_per_particle=s["n_acc"] / n,
+                         status_counts=s["status_counts"],
+                         drift_median={k: float(np.median(drift[i])) for i, k in enumerate(("E", "Lz", "Q", "mu2"))},
+                         drift_p99={k: float(np.quantile(drift[i], 0.99)) for i, k in enumerate(("E", "Lz", "Q", "mu2"))})
+        finals[name] = (st.s.cpu().numpy(), landed)
+        log(f"particles {name}: {dt:.3f} s, {s['n_acc'] / n:.0f} steps/particle")
+    (s64, l64), (s32, l32) = finals["fp64"], finals["fp32"]
+    both = l64 & l32
+    d = np.linalg.norm(s32[1:4, both] - s64[1:4, both], axis=0) / np.linalg.norm(s64[1:4, both], axis=0)
+    out["fp32_vs_fp64_position"] = dict(median=float(np.median(d)), p99=float(np.quantile(d, 0.99)))
+    return out
 
 
 def copy_probe(mib):

@@ -26,7 +26,7 @@ using namespace kh;
 
 // The Python binding mirrors these layouts with ctypes.
 static_assert(sizeof(kh_camera) == 64, "kh_camera layout");
-static_assert(sizeof(kh_params) == 104, "kh_params layout");
+static_assert(sizeof(kh_params) == 112, "kh_params layout");
 static_assert(sizeof(kh_state) == 120, "kh_state layout");
 
 namespace {
@@ -57,6 +57,7 @@ struct KParams {
   int64_t max_steps;
   int32_t k_cross;
   int32_t refill_min;
+  int32_t parts;  // ray-range partitions of the work queue (1 .. kParts)
 };
 
 KState to_k(const kh_state* st) {
@@ -114,24 +115,34 @@ __global__ void k_reset_counters(unsigned long long* q, int n) {
   if (threadIdx.x < n) q[threadIdx.x] = 0ull;
 }
 
-// Work stealing over kParts contiguous partitions of the ray range.  A wave
-// starts on the partition of its XCD (workgroups are dispatched round-robin
-// over the XCDs, so blockIdx.x % kParts), which keeps a refill's neighbouring
-// ids in that XCD's L2, and moves on to the next partition when its own is
-// drained.  One atomic per refill; lane offsets from mbcnt over the ballot of
-// idle lanes.  Wave-uniform call; `cursor` counts partitions already drained
-// by this wave (kParts = all work handed out).  Returns the lane's new id or -1.
+// Work stealing over `parts` partitions of the ray range.  The range is cut
+// into chunks of kChunk consecutive ids dealt round-robin to the partitions
+// (partition p owns chunks p, p + parts, ...), so every partition advances
+// through the images at the same pace and the queue still ends on the last
+// rows of the images (the cheap edge rays) instead of several partitions ending
+// on expensive rays.  A wave starts on the partition of its XCD (workgroups
+// are dispatched round-robin over the XCDs: blockIdx.x % parts), so a refill's
+// neighbouring ids stay in one L2, and moves on to the next partition when its
+// own is drained.  One atomic per refill; lane offsets from mbcnt over the
+// ballot of idle lanes.  Wave-uniform call; `cursor` counts partitions this
+// wave has seen drained (== parts: all work handed out).  Returns the lane's
+// new id or -1.
+constexpr int64_t kChunk = 8192;
+
 __device__ inline int64_t wave_grab(unsigned long long idle, unsigned long long* qctr, int64_t n, int home,
-                                    int& cursor) {
+                                    int parts, int& cursor) {
   const int cnt = __popcll(idle);
   const int leader = __ffsll((long long)idle) - 1;
   const int lane = __lane_id();
   const unsigned rank =
       __builtin_amdgcn_mbcnt_hi((unsigned)(idle >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)idle, 0u));
-  while (cursor < kParts) {
-    const int p = (home + cursor) % kParts;
-    const int64_t lo = n * p / kParts, hi = n * (p + 1) / kParts;
-    const unsigned long long size = (unsigned long long)(hi - lo);
+  const int64_t n_chunks = (n + kChunk - 1) / kChunk;
+  const int64_t tail = n - (n_chunks - 1) * kChunk;  // length of the last chunk
+  while (cursor < parts) {
+    const int p = (home + cursor) % parts;
+    const int64_t my_chunks = p < n_chunks ? (n_chunks - 1 - p) / parts + 1 : 0;
+    const bool owns_last = my_chunks > 0 && (n_chunks - 1) % parts == p;
+    const unsigned long long size = (unsigned long long)(my_chunks * kChunk - (owns_last ? kChunk - tail : 0));
     unsigned long long base = 0;
     if (lane == leader) base = atomicAdd(qctr + p, (unsigned long long)cnt);
     base = __shfl(base, leader);
@@ -139,7 +150,8 @@ __device__ inline int64_t wave_grab(unsigned long long idle, unsigned long long*
       if (base + (unsigned long long)cnt >= size) ++cursor;  // this grab drains the partition
       if (!((idle >> lane) & 1ull)) return -1;
       const unsigned long long off = base + rank;
-      return off < size ? lo + (int64_t)off : -1;
+      if (off >= size) return -1;
+      return ((int64_t)(off / kChunk) * parts + p) * kChunk + (int64_t)(off % kChunk);
     }
     ++cursor;
   }
@@ -160,7 +172,8 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
 
   const int64_t n = S.n;
   int64_t ray = -1;
-  const int home = blockIdx.x % kParts;
+  const int parts = P.parts;
+  const int home = blockIdx.x % parts;
   int cursor = 0;  // partitions this wave has seen drained (wave-uniform)
   bool fresh = false;
 
@@ -179,8 +192,8 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
   while (true) {
     // ---- refill idle lanes (wave-uniform decision) ----
     const unsigned long long idle = __ballot(ray < 0);
-    if (cursor < kParts && idle != 0ull && (__popcll(idle) >= P.refill_min || idle == ~0ull)) {
-      const int64_t id = wave_grab(idle, qctr, n, home, cursor);
+    if (cursor < parts && idle != 0ull && (__popcll(idle) >= P.refill_min || idle == ~0ull)) {
+      const int64_t id = wave_grab(idle, qctr, n, home, parts, cursor);
       if (ray < 0 && id >= 0) {
         const int st = S.status[id];
         if (st == KH_ACTIVE || st == KH_MAX_STEPS) {
@@ -210,7 +223,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
       }
     }
     if (__ballot(ray >= 0) == 0ull) {
-      if (cursor >= kParts) break;
+      if (cursor >= parts) break;
       continue;
     }
     if (ray < 0) continue;
@@ -901,10 +914,11 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
     return fail(ctx, KH_EUNSUPPORTED, "the paper-form right-hand side is built for P64 and P32 only");
   const int block = p->block_size ? p->block_size : 256;
   if (block < 64 || block > 256 || block % 64) return fail(ctx, KH_EINVAL, "block_size must be 64, 128, 192 or 256");
-  const int refill = p->refill_min ? p->refill_min : 4;
+  const int refill = p->refill_min ? p->refill_min : 16;
   if (refill < 1 || refill > 64) return fail(ctx, KH_EINVAL, "refill_min must be in [1, 64]");
   if (p->grid_blocks < 0) return fail(ctx, KH_EINVAL, "grid_blocks must be >= 0");
   if (p->waves_per_eu < 0 || p->waves_per_eu > 8) return fail(ctx, KH_EINVAL, "waves_per_eu must be in [0, 8]");
+  if (p->queue_parts < 0 || p->queue_parts > kParts) return fail(ctx, KH_EINVAL, "queue_parts must be in [0, 8]");
   kh_status s = check_state(ctx, st, p->k_cross > 0);
   if (s != KH_OK) return s;
   if (p->k_cross > st->k_cross) return fail(ctx, KH_EINVAL, "params.k_cross exceeds state.k_cross");
@@ -926,6 +940,7 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   kp.max_steps = p->max_steps;
   kp.k_cross = p->k_cross;
   kp.refill_min = refill;
+  kp.parts = p->queue_parts ? p->queue_parts : kParts;
 
   void* fn = pick_kernel(p->method, p->precision, p->rhs_form, p->waves_per_eu ? p->waves_per_eu : 1);
   if (!fn) return fail(ctx, KH_EUNSUPPORTED, "no kernel for this method / precision / rhs_form / waves_per_eu");

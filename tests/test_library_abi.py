@@ -52,7 +52,7 @@ def test_default_params_and_struct_layout():
     assert p.r_h_factor == 1.01 and p.r_escape == 1000.0 and p.max_steps == 1_000_000
     # struct sizes agree with the C layout (8-byte aligned doubles)
     assert C.sizeof(K.kh_camera) == 64
-    assert C.sizeof(K.kh_params) == 104
+    assert C.sizeof(K.kh_params) == 112
     assert C.sizeof(K.kh_state) == 8 * 15
 
 
