@@ -159,6 +159,55 @@ __device__ inline int64_t wave_grab(unsigned long long idle, unsigned long long*
 }
 
 // ---------------------------------------------------------------------------
+// Equatorial crossings: a lane that sees a sign change of z only queues the
+// two nodes of the step in its wave's LDS queue; the wave refines queued
+// crossings together, one per lane, once the queue is nearly full and when it
+// exits.  This keeps the root find, the two arctangents and the redshift out
+// of the divergent per-lane path (a crossing in any lane would otherwise stall
+// the other 63).  Field-major layout: field f of record j at f * kQCap + j.
+// ---------------------------------------------------------------------------
+constexpr int kQCap = 96;
+enum { QX0, QY0, QZ0, QKX0, QKY0, QKZ0, QX1, QY1, QZ1, QK01, QKX1, QKY1, QKZ1, QH, QAC, QWIND, QTAG, kQFields };
+
+__device__ inline void refine_crossing(const double* q, int j, const KState& S) {
+  const double x0 = q[QX0 * kQCap + j], y0 = q[QY0 * kQCap + j], z0 = q[QZ0 * kQCap + j];
+  const double x1 = q[QX1 * kQCap + j], y1 = q[QY1 * kQCap + j], z1 = q[QZ1 * kQCap + j];
+  const double h = q[QH * kQCap + j], ac = q[QAC * kQCap + j];
+  const int64_t tag = (int64_t)q[QTAG * kQCap + j];  // (ray * 8 + slot) * 2 + kind
+  const int kind = (int)(tag & 1);
+  const int slot = (int)((tag >> 1) & 7);
+  const int64_t ray = tag >> 4;
+  const double phi0 = atan2(y0, x0) + (2.0 * M_PI) * q[QWIND * kQCap + j];
+  const double th = hermite_zero(z0, q[QKZ0 * kQCap + j], z1, q[QKZ1 * kQCap + j], h);
+  const double xc = herm(th, x0, q[QKX0 * kQCap + j], x1, q[QKX1 * kQCap + j], h);
+  const double yc = herm(th, y0, q[QKY0 * kQCap + j], y1, q[QKY1 * kQCap + j], h);
+  const double qq = xc * xc + yc * yc - ac * ac;
+  const double rc = sqrt(qq > 0.0 ? qq : 0.0);
+  const double phic = phi0 + atan2(x0 * yc - y0 * xc, x0 * xc + y0 * yc);
+  const double xd[4] = {0.0, x1, y1, z1};
+  const double kd[4] = {q[QK01 * kQCap + j], q[QKX1 * kQCap + j], q[QKY1 * kQCap + j], q[QKZ1 * kQCap + j]};
+  const double xi = photon_xi(ac, xd, kd, kind == KH_NULL);
+  const double g = redshift(rc, xi, kind == KH_NULL ? -ac : ac);
+  double* out = S.cross + (ray * S.k_cross + slot) * 3;
+  out[0] = rc;
+  out[1] = phic;
+  out[2] = g;
+}
+
+// Whole-wave call: refine records [0, count) of this wave's queue.
+__device__ inline void flush_crossings(double* q, int* qcnt, int count, const KState& S) {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int lane = __lane_id();
+  for (int b = 0; b < count; b += 64)
+    if (b + lane < count) refine_crossing(q, b + lane, S);
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) *qcnt = 0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------------------
 // Persistent integrate kernel.
 // METHOD: KH_RK4 / KH_DOPRI5.  PREC: KH_P64 / KH_P32 / KH_PMIXED.
 // FORM: right-hand-side evaluation (KH_RHS_FACTORED / KH_RHS_PAPER).
@@ -172,6 +221,16 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
 
   const int64_t n = S.n;
   int64_t ray = -1;
+  // per-wave crossing queue in dynamic LDS (present when crossings are recorded)
+  extern __shared__ double kh_lds[];
+  const int wave_in_block = threadIdx.x >> 6;
+  double* cq = kh_lds + (size_t)wave_in_block * (kQFields * kQCap + 1);
+  int* cq_count = reinterpret_cast<int*>(cq + kQFields * kQCap);
+  if (P.k_cross > 0) {
+    if (__lane_id() == 0) *cq_count = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
   const int parts = P.parts;
   const int home = blockIdx.x % parts;
   int cursor = 0;  // partitions this wave has seen drained (wave-uniform)
@@ -190,6 +249,13 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
   bool after_reject = false;
 
   while (true) {
+    // ---- refine queued crossings with the whole wave (uniform point) ----
+    if (P.k_cross > 0) {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const int qc = *cq_count;
+      if (qc > kQCap - 64) flush_crossings(cq, cq_count, qc, S);
+    }
     // ---- refill idle lanes (wave-uniform decision) ----
     const unsigned long long idle = __ballot(ray < 0);
     if (cursor < parts && idle != 0ull && (__popcll(idle) >= P.refill_min || idle == ~0ull)) {
@@ -298,34 +364,32 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
           status = KH_FAILED;
         } else {
           if (P.k_cross > 0) {
-            // Unwrapped azimuth and equatorial crossings between the two nodes.
+            // Unwrapped azimuth; equatorial crossings are queued for the wave.
             const double x0 = x[1], y0 = x[2], z0 = x[3];
             const double x1 = xn[1], y1 = xn[2], z1 = xn[3];
             const int wind0 = wind;
-            const double cr = x0 * y1 - y0 * x1;
-            wind += (y0 >= 0.0 && y1 < 0.0 && cr > 0.0) - (y0 < 0.0 && y1 >= 0.0 && cr < 0.0);
+            const double crs = x0 * y1 - y0 * x1;
+            wind += (y0 >= 0.0 && y1 < 0.0 && crs > 0.0) - (y0 < 0.0 && y1 >= 0.0 && crs < 0.0);
             if ((z0 < 0.0 && z1 > 0.0) || (z0 > 0.0 && z1 < 0.0) || (z1 == 0.0 && z0 != 0.0)) {
-              const double phi0 = atan2(y0, x0) + (2.0 * M_PI) * wind0;
-              const double th = hermite_zero(z0, (double)k[3], z1, (double)kn[3], h);
-              const double xc = herm(th, x0, (double)k[1], x1, (double)kn[1], h);
-              const double yc = herm(th, y0, (double)k[2], y1, (double)kn[2], h);
-              const double ac = (double)a_c;
-              const double q = xc * xc + yc * yc - ac * ac;
-              const double rc = sqrt(q > 0.0 ? q : 0.0);
-              const double phic = phi0 + atan2(x0 * yc - y0 * xc, x0 * xc + y0 * yc);
-              double xd[4], kd[4];
-#pragma unroll
-              for (int c = 0; c < 4; ++c) {
-                xd[c] = (double)xn[c];
-                kd[c] = (double)kn[c];
-              }
-              const double xi = photon_xi(ac, xd, kd, kind == KH_NULL);
-              const double g = redshift(rc, xi, a_phys);
               if (ncross < S.k_cross && ncross < P.k_cross) {
-                double* cr = S.cross + ((int64_t)ray * S.k_cross + ncross) * 3;
-                cr[0] = rc;
-                cr[1] = phic;
-                cr[2] = g;
+                const int j = atomicAdd(cq_count, 1);  // < kQCap: flushed before 64 more can arrive
+                cq[QX0 * kQCap + j] = x0;
+                cq[QY0 * kQCap + j] = y0;
+                cq[QZ0 * kQCap + j] = z0;
+                cq[QKX0 * kQCap + j] = (double)k[1];
+                cq[QKY0 * kQCap + j] = (double)k[2];
+                cq[QKZ0 * kQCap + j] = (double)k[3];
+                cq[QX1 * kQCap + j] = x1;
+                cq[QY1 * kQCap + j] = y1;
+                cq[QZ1 * kQCap + j] = z1;
+                cq[QK01 * kQCap + j] = (double)kn[0];
+                cq[QKX1 * kQCap + j] = (double)kn[1];
+                cq[QKY1 * kQCap + j] = (double)kn[2];
+                cq[QKZ1 * kQCap + j] = (double)kn[3];
+                cq[QH * kQCap + j] = h;
+                cq[QAC * kQCap + j] = (double)a_c;
+                cq[QWIND * kQCap + j] = (double)wind0;
+                cq[QTAG * kQCap + j] = (double)(((ray * 8 + ncross) << 1) | (kind == KH_NULL ? 0 : 1));
               }
               ++ncross;
             }
@@ -393,20 +457,34 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
       S.n_acc[ray] = nacc;
       S.n_rej[ray] = nrej;
       if (S.n_cross) S.n_cross[ray] = ncross;
-      if (S.c1) {
-        double xd[4], kd[4], cst[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          xd[c] = (double)x[c];
-          kd[c] = (double)k[c];
-        }
-        constants((double)a_c, xd, kd, cst);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) S.c1[q * n + ray] = cst[q];
-      }
       ray = -1;
     }
   }
+  if (P.k_cross > 0) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int qc = *cq_count;
+    if (qc > 0) flush_crossings(cq, cq_count, qc, S);
+  }
+}
+
+// Constants of motion of every ray's current state (after an integrate call),
+// in FP64, fully parallel.  Rays the call skipped keep the same state, so
+// recomputing theirs reproduces the earlier value.
+__global__ void k_constants_end(KState S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = S.n;
+  if (i >= n) return;
+  double x[4], k[4], cst[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    x[c] = S.s[c * n + i];
+    k[c] = S.s[(4 + c) * n + i];
+  }
+  const double a = S.spin[i];
+  constants(S.kind[i] == KH_NULL ? -a : a, x, k, cst);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) S.c1[q * n + i] = cst[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -944,10 +1022,12 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
 
   void* fn = pick_kernel(p->method, p->precision, p->rhs_form, p->waves_per_eu ? p->waves_per_eu : 1);
   if (!fn) return fail(ctx, KH_EUNSUPPORTED, "no kernel for this method / precision / rhs_form / waves_per_eu");
+  // dynamic LDS: one crossing queue (kQFields x kQCap doubles + a counter) per wave
+  const size_t lds = p->k_cross > 0 ? (size_t)(block / 64) * (kQFields * kQCap + 1) * sizeof(double) : 0;
   int grid = p->grid_blocks;
   if (grid == 0) {
     int per_cu = 0;
-    KH_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, block, 0));
+    KH_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, block, lds));
     grid = std::max(1, per_cu) * ctx->n_cu;
   }
   const int64_t need = (st->n + block - 1) / block;
@@ -958,7 +1038,12 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   KH_HIP(ctx, hipGetLastError());
   const KState ks = to_k(st);
   void* args[] = {(void*)&kp, (void*)&ks, (void*)&q};
-  KH_HIP(ctx, hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, strm));
+  KH_HIP(ctx, hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, strm));
+  if (st->c1) {
+    const int b = 256;
+    hipLaunchKernelGGL(k_constants_end, dim3((unsigned)((st->n + b - 1) / b)), dim3(b), 0, strm, ks);
+    KH_HIP(ctx, hipGetLastError());
+  }
   return KH_OK;
 }
 
