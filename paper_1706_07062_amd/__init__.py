@@ -52,8 +52,24 @@ class kh_flop_counts(C.Structure):
                 ("step_sqrt", C.c_int64)]
 
 
+class kh_mlp(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p), ("wb", C.c_void_p),
+                ("wbt", C.c_void_p)]
+
+
+class kh_adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("step", C.c_int32)]
+
+
+MLP_NPARAMS = 199684
+MLP_WB_ELEMS = 208896
+MLP_WBT_ELEMS = 204800
+
 EXPORTS = ["kh_create", "kh_destroy", "kh_last_error", "kh_default_params", "kh_init_rays", "kh_init_rays_list",
            "kh_init_geodesics", "kh_integrate", "kh_read_state", "kh_stats", "kh_stats_device", "kh_rhs", "kh_flops"]
+MLP_EXPORTS = ["kh_mlp_work_bytes", "kh_mlp_sync", "kh_mlp_forward", "kh_mlp_image", "kh_mlp_targets", "kh_mlp_grad",
+               "kh_mlp_train_step", "kh_init_rays_pixels", "kh_image_from_state"]
 
 _lib = None
 
@@ -83,8 +99,18 @@ def lib():
         L.kh_stats_device.argtypes = [vp, P(kh_state), vp, vp]
         L.kh_rhs.argtypes = [vp, i32, i32, vp, vp, vp, i64, vp]
         L.kh_flops.argtypes = [i32, i32, P(kh_flop_counts)]
-        for name in EXPORTS:
-            if name not in ("kh_last_error", "kh_default_params"):
+        L.kh_mlp_work_bytes.argtypes = [i32]
+        L.kh_mlp_work_bytes.restype = i64
+        L.kh_mlp_sync.argtypes = [vp, P(kh_mlp), vp]
+        L.kh_mlp_forward.argtypes = [vp, P(kh_mlp), vp, vp, i64, vp]
+        L.kh_mlp_image.argtypes = [vp, P(kh_mlp), P(kh_camera), C.c_float, vp, vp, vp, vp]
+        L.kh_mlp_targets.argtypes = [vp, P(kh_state), vp, vp, vp, vp, vp, vp, vp, vp]
+        L.kh_mlp_grad.argtypes = [vp, P(kh_mlp), vp, i32, vp, vp, vp, i32, vp, vp, vp]
+        L.kh_mlp_train_step.argtypes = [vp, P(kh_mlp), vp, i32, vp, vp, vp, i32, P(kh_adam), vp, vp]
+        L.kh_init_rays_pixels.argtypes = [vp, P(kh_camera), vp, P(kh_state), vp]
+        L.kh_image_from_state.argtypes = [vp, P(kh_state), vp, vp, vp]
+        for name in EXPORTS + MLP_EXPORTS:
+            if name not in ("kh_last_error", "kh_default_params", "kh_mlp_work_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -212,6 +238,95 @@ class Context:
 def _check_vec(t, n):
     if t.dtype != torch.float64 or not t.is_cuda or t.numel() != n or not t.is_contiguous():
         raise ValueError(f"expected a contiguous float64 CUDA tensor with {n} elements")
+
+
+def _dev(t, dtype, n=None, align=16):
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or (n is not None and t.numel() != n):
+        raise ValueError(f"expected a contiguous {dtype} CUDA tensor" + (f" with {n} elements" if n else ""))
+    if t.data_ptr() % align:
+        raise ValueError(f"tensor must be {align}-byte aligned")
+    return t.data_ptr()
+
+
+class Mlp:
+    """Surrogate network tensors (FP32 master weights, Adam moments, BF16 copies)."""
+
+    def __init__(self, params=None, train=True, device="cuda"):
+        import numpy as np
+
+        f32 = dict(dtype=torch.float32, device=device)
+        if params is None:
+            params = np.zeros(MLP_NPARAMS, np.float32)
+        self.params = torch.tensor(np.asarray(params, np.float32), **f32)
+        self.adam_m = torch.zeros(MLP_NPARAMS, **f32) if train else None
+        self.adam_v = torch.zeros(MLP_NPARAMS, **f32) if train else None
+        self.wb = torch.zeros(MLP_WB_ELEMS, dtype=torch.int16, device=device)
+        self.wbt = torch.zeros(MLP_WBT_ELEMS, dtype=torch.int16, device=device) if train else None
+        p = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        self.c = kh_mlp(p(self.params), p(self.adam_m), p(self.adam_v), p(self.wb), p(self.wbt))
+
+
+def kh_mlp_work_bytes(max_batch: int) -> int:
+    return lib().kh_mlp_work_bytes(max_batch)
+
+
+def _mlp_methods():
+    def kh_mlp_sync(self, net: Mlp, stream=None):
+        self._check(lib().kh_mlp_sync(self.handle, C.byref(net.c), _stream(stream)), "kh_mlp_sync")
+
+    def kh_mlp_forward(self, net: Mlp, x, y, stream=None):
+        m = x.shape[0]
+        _dev(x, torch.float32, 4 * m)
+        _dev(y, torch.float32, 4 * m)
+        self._check(lib().kh_mlp_forward(self.handle, C.byref(net.c), x.data_ptr(), y.data_ptr(), m,
+                                         _stream(stream)), "kh_mlp_forward")
+
+    def kh_mlp_image(self, net: Mlp, cam: kh_camera, tau, out, fb_ids, fb_count, stream=None):
+        npix = cam.width * cam.height
+        _dev(out, torch.float32, 4 * npix)
+        _dev(fb_ids, torch.int32, npix, align=4)
+        _dev(fb_count, torch.int32, 1, align=4)
+        self._check(lib().kh_mlp_image(self.handle, C.byref(net.c), C.byref(cam), float(tau), out.data_ptr(),
+                                       fb_ids.data_ptr(), fb_count.data_ptr(), _stream(stream)), "kh_mlp_image")
+
+    def kh_mlp_targets(self, st: "State", alpha, beta, spin, incl, x, t, mask, stream=None):
+        for v in (alpha, beta, spin, incl):
+            _dev(v, torch.float64, st.n, align=8)
+        _dev(x, torch.float32, 4 * st.n)
+        _dev(t, torch.float32, 4 * st.n)
+        _dev(mask, torch.uint8, st.n, align=1)
+        self._check(lib().kh_mlp_targets(self.handle, C.byref(st.c), alpha.data_ptr(), beta.data_ptr(),
+                                         spin.data_ptr(), incl.data_ptr(), x.data_ptr(), t.data_ptr(),
+                                         mask.data_ptr(), _stream(stream)), "kh_mlp_targets")
+
+    def kh_mlp_grad(self, net: Mlp, work, max_batch, x, t, mask, b, grad, loss, stream=None):
+        _dev(grad, torch.float32, MLP_NPARAMS)
+        self._check(lib().kh_mlp_grad(self.handle, C.byref(net.c), work.data_ptr(), max_batch, x.data_ptr(),
+                                      t.data_ptr(), mask.data_ptr(), b, grad.data_ptr(), loss.data_ptr(),
+                                      _stream(stream)), "kh_mlp_grad")
+
+    def kh_mlp_train_step(self, net: Mlp, work, max_batch, x, t, mask, b, opt: kh_adam, loss, stream=None):
+        self._check(lib().kh_mlp_train_step(self.handle, C.byref(net.c), work.data_ptr(), max_batch, x.data_ptr(),
+                                            t.data_ptr(), mask.data_ptr(), b, C.byref(opt), loss.data_ptr(),
+                                            _stream(stream)), "kh_mlp_train_step")
+
+    def kh_init_rays_pixels(self, cam: kh_camera, pix, st: "State", stream=None):
+        _dev(pix, torch.int32, st.n, align=4)
+        self._check(lib().kh_init_rays_pixels(self.handle, C.byref(cam), pix.data_ptr(), C.byref(st.c),
+                                              _stream(stream)), "kh_init_rays_pixels")
+
+    def kh_image_from_state(self, st: "State", pix, out, stream=None):
+        if pix is not None:
+            _dev(pix, torch.int32, st.n, align=4)
+        self._check(lib().kh_image_from_state(self.handle, C.byref(st.c), pix.data_ptr() if pix is not None else None,
+                                              out.data_ptr(), _stream(stream)), "kh_image_from_state")
+
+    for f in (kh_mlp_sync, kh_mlp_forward, kh_mlp_image, kh_mlp_targets, kh_mlp_grad, kh_mlp_train_step,
+              kh_init_rays_pixels, kh_image_from_state):
+        setattr(Context, f.__name__, f)
+
+
+_mlp_methods()
 
 
 class State:

@@ -19,10 +19,13 @@
 #include <vector>
 
 #include "kerrhip.h"
+#include "kerrhip_mlp.h"
 #include "ks_math.hpp"
 #include "steppers.hpp"
+#include "internal.hpp"
 
 using namespace kh;
+using namespace khi;
 
 // The Python binding mirrors these layouts with ctypes.
 static_assert(sizeof(kh_camera) == 64, "kh_camera layout");
@@ -33,52 +36,6 @@ namespace {
 
 constexpr int kQueueSlots = 16;  // work-queue counters per context
 constexpr int kParts = 8;        // ray-range partitions = XCDs of an MI355X
-
-struct KState {
-  int64_t n;
-  double* s;
-  double* spin;
-  int32_t* kind;
-  double* h;
-  double* lam;
-  double* phi;
-  int32_t* status;
-  int32_t* n_acc;
-  int32_t* n_rej;
-  double* cross;
-  int32_t* n_cross;
-  int32_t k_cross;
-  double* c0;
-  double* c1;
-};
-
-struct KParams {
-  double h_coeff, rtol, atol, hmax_coeff, r_h_factor, r_escape, t_end, r_fp64;
-  int64_t max_steps;
-  int32_t k_cross;
-  int32_t refill_min;
-  int32_t parts;  // ray-range partitions of the work queue (1 .. kParts)
-};
-
-KState to_k(const kh_state* st) {
-  KState k;
-  k.n = st->n;
-  k.s = st->s;
-  k.spin = st->spin;
-  k.kind = st->kind;
-  k.h = st->h;
-  k.lam = st->lam;
-  k.phi = st->phi;
-  k.status = st->status;
-  k.n_acc = st->n_acc;
-  k.n_rej = st->n_rej;
-  k.cross = st->cross;
-  k.n_cross = st->n_cross;
-  k.k_cross = st->k_cross;
-  k.c0 = st->c0;
-  k.c1 = st->c1;
-  return k;
-}
 
 __device__ inline double hscale(int kind, double r) { return kind == KH_TIMELIKE ? r * sqrt(r) : r; }
 
@@ -551,6 +508,19 @@ __global__ void k_init_rays(const kh_camera* cams, const int64_t* offs, int n_ca
   finish_init(S, i, y, cam.a, KH_NULL, ok);
 }
 
+__global__ void k_init_rays_pixels(kh_camera cam, const int32_t* pix, KState S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  const int64_t p = pix[i];
+  const int64_t row = p / cam.width, col = p % cam.width;
+  const double al = cam.alpha_min + (col + 0.5) * (cam.alpha_max - cam.alpha_min) / cam.width;
+  const double be = cam.beta_min + (row + 0.5) * (cam.beta_max - cam.beta_min) / cam.height;
+  double y[8];
+  bool ok;
+  camera_ray(cam.a, cam.r_obs, cam.incl, al, be, y, &ok);
+  finish_init(S, i, y, cam.a, KH_NULL, ok);
+}
+
 __global__ void k_init_rays_list(const double* spin, const double* incl, const double* alpha, const double* beta,
                                  double r_obs, KState S) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -673,23 +643,8 @@ inline Cnt kmax(Cnt x, Cnt y) { return x.v > y.v ? x : y; }
 // ---------------------------------------------------------------------------
 // Context and C ABI.
 // ---------------------------------------------------------------------------
-struct kh_ctx {
-  int device = 0;
-  int n_cu = 0;
-  unsigned long long* d_queue = nullptr;  // kQueueSlots counters
-  unsigned long long* d_stats = nullptr;  // 8 counters
-  kh_camera* d_cams = nullptr;
-  int64_t* d_offs = nullptr;
-  int cam_cap = 0;
-  int cams_uploaded = 0;        // cameras currently in d_cams / d_offs
-  int64_t cams_total = 0;       // their total pixel count
-  kh_camera* h_cams = nullptr;  // pinned staging
-  int64_t* h_offs = nullptr;
-  hipEvent_t cam_evt = nullptr;
-  std::string err;
-};
 
-namespace {
+namespace khi {
 
 kh_status fail(kh_ctx* c, kh_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -700,12 +655,6 @@ kh_status hip_fail(kh_ctx* c, hipError_t e, const char* where) {
   std::string m = std::string(where) + ": " + hipGetErrorString(e);
   return fail(c, KH_EHIP, m);
 }
-
-#define KH_HIP(ctx, call)                                 \
-  do {                                                    \
-    hipError_t e_ = (call);                               \
-    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
-  } while (0)
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
@@ -732,7 +681,7 @@ bool capturing(void* stream) {
   return cs == hipStreamCaptureStatusActive;
 }
 
-thread_local bool g_skip_ptr_query = false;
+thread_local bool g_skip_ptr_query = false;  // set per entry point while its stream is capturing
 
 bool device_ok(const void* p) { return g_skip_ptr_query ? p != nullptr : is_device_ptr(p); }
 
@@ -763,6 +712,12 @@ kh_status set_device(kh_ctx* ctx) {
   KH_HIP(ctx, hipSetDevice(ctx->device));
   return KH_OK;
 }
+
+}  // namespace khi
+
+using namespace khi;
+
+namespace {
 
 template <int M, int P, int F, int W>
 void* kernel_ptr() {
@@ -946,6 +901,23 @@ kh_status kh_init_rays_list(kh_ctx* ctx, const double* spin, const double* incl,
   const int64_t grid = (st->n + block - 1) / block;
   hipLaunchKernelGGL(k_init_rays_list, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)stream, spin, incl, alpha,
                      beta, r_obs, ks);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+kh_status kh_init_rays_pixels(kh_ctx* ctx, const kh_camera* cam, const int32_t* pix, kh_state* st, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = capturing(stream);
+  if (!cam || !(std::fabs(cam->a) <= 1.0) || !(cam->r_obs > 0.0) || cam->width < 1 || cam->height < 1)
+    return fail(ctx, KH_EINVAL, "camera: need |a| <= 1, r_obs > 0, width, height >= 1");
+  kh_status s = check_state(ctx, st, false);
+  if (s != KH_OK) return s;
+  if (!pix || !aligned(pix, 4) || !device_ok(pix)) return fail(ctx, KH_EINVAL, "pix must be device int32 [n]");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  const KState ks = to_k(st);
+  const int block = 256;
+  hipLaunchKernelGGL(k_init_rays_pixels, dim3((unsigned)((st->n + block - 1) / block)), dim3(block), 0,
+                     (hipStream_t)stream, *cam, pix, ks);
   KH_HIP(ctx, hipGetLastError());
   return KH_OK;
 }

@@ -1,0 +1,690 @@
+// mlp.hip -- the surrogate network (include/kerrhip_mlp.h) on the BF16 matrix cores.
+//
+// Every product is written as D^T = W X^T: the weight tile is the MFMA A
+// operand (32 output features x 16 inputs, read straight from L2 as 16-byte
+// rows of the [out][in] BF16 copy) and the activations are the B operand
+// (16 inputs x 32 rays, read as 16-byte rows of a per-wave LDS tile
+// [ray][feature]).  The 32x32 accumulator then holds, per lane, four
+// consecutive output features of one ray, so bias, SiLU and the BF16 store of
+// the next activation row are one 8-byte write.  One wave owns 32 rays and
+// carries them through all five layers without leaving the CU.
+//
+// MFMA operand layout used (v_mfma_f32_32x32x16_bf16, 64 lanes):
+//   A[i][k]: lane l holds i = l % 32, k = 8 (l / 32) + j, j = 0..7
+//   B[k][n]: lane l holds n = l % 32, k = 8 (l / 32) + j
+//   D[i][n]: lane l, element e holds i = 8 (e / 4) + 4 (l / 32) + e % 4, n = l % 32
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "internal.hpp"
+#include "kerrhip_mlp.h"
+
+using namespace khi;
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NP = KH_MLP_NPARAMS;
+constexpr int HID = 256;
+constexpr int RAYS = 32;        // rays per wave
+constexpr int LDA = HID + 8;    // LDS row stride (BF16) of the activation tile
+constexpr int SPLITS = 16;      // batch splits of the weight-gradient products
+constexpr int HT0_ROWS = 32;    // input features padded to one 32-row tile
+
+// FP32 parameter offsets: W_l [out][in], then b_l.
+__device__ __constant__ int OFF_W[5] = {0, 1280, 67072, 132864, 198656};
+__device__ __constant__ int OFF_B[5] = {1024, 66816, 132608, 198400, 199680};
+constexpr int h_OFF_W[5] = {0, 1280, 67072, 132864, 198656};
+constexpr int h_OFF_B[5] = {1024, 66816, 132608, 198400, 199680};
+constexpr int IN_DIM[5] = {4, 256, 256, 256, 256};
+constexpr int OUT_DIM[5] = {256, 256, 256, 256, 4};
+// BF16 forward copies: layer l is [MPAD_l][KPAD_l] with zero padding.
+constexpr int KPAD[5] = {16, 256, 256, 256, 256};
+constexpr int MPAD[5] = {256, 256, 256, 256, 32};
+constexpr int OFF_WB[5] = {0, 4096, 69632, 135168, 200704};
+// BF16 transposed copies of layers 1..4: [KPAD_l][MPAD_l].
+constexpr int OFF_WBT[5] = {0, 0, 65536, 131072, 196608};
+
+static_assert(OFF_WB[4] + 32 * 256 == KH_MLP_WB_ELEMS, "forward copy size");
+static_assert(OFF_WBT[4] + 256 * 32 == KH_MLP_WBT_ELEMS, "transposed copy size");
+
+// Input and target normalisation.
+__device__ inline void norm_features(float alpha, float beta, float a, float incl, float f[4]) {
+  f[0] = alpha * (1.0f / 12.0f);
+  f[1] = beta * (1.0f / 12.0f);
+  f[2] = (a - 0.5f) * 2.0f;
+  f[3] = (incl * (180.0f / 3.14159265358979f) - 45.0f) * (1.0f / 40.0f);
+}
+
+__device__ inline float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
+__device__ inline float silu(float z) { return z * sigmoidf(z); }
+__device__ inline float dsilu(float z) {
+  const float s = sigmoidf(z);
+  return s * (1.0f + z * (1.0f - s));
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+struct FwdArgs {
+  const float* params;
+  const __bf16* wb;
+  const float* x;  // raw features [m][4] (modes 0 and 2)
+  int64_t m;
+  kh_camera cam;   // mode 1
+  float* y;        // raw outputs [m][4] (modes 0, 2) or decoded image (mode 1)
+  float tau;
+  int32_t* fb_ids;
+  int32_t* fb_count;
+  float* z;    // mode 2: pre-activations [4][bmax][256]
+  __bf16* ht;  // mode 2: HT_0 [32][bmax], then HT_1..HT_4 [256][bmax]
+  int64_t bmax;
+};
+
+__host__ __device__ inline __bf16* ht_layer(__bf16* ht, int l, int64_t bmax) {
+  return l == 0 ? ht : ht + (int64_t)HT0_ROWS * bmax + (int64_t)(l - 1) * HID * bmax;
+}
+
+// Bias, SiLU and the stores of one hidden layer's accumulators.
+template <int MODE>
+__device__ inline void store_hidden(const FwdArgs& A, int l, const f32x16 (&acc)[8], __bf16* act, int r, int half,
+                                    int64_t ray, bool valid) {
+  const float* bias = A.params + OFF_B[l];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int m0 = t * 32 + 8 * g + 4 * half;
+      const f32x4 b = *reinterpret_cast<const f32x4*>(bias + m0);
+      f32x4 zz;
+      bf16x4 hv;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        zz[q] = acc[t][4 * g + q] + b[q];
+        hv[q] = (__bf16)silu(zz[q]);
+      }
+      *reinterpret_cast<bf16x4*>(act + r * LDA + m0) = hv;
+      if (MODE == 2 && valid) {
+        *reinterpret_cast<f32x4*>(A.z + ((int64_t)l * A.bmax + ray) * HID + m0) = zz;
+        __bf16* ht = ht_layer(A.ht, l + 1, A.bmax);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ht[(int64_t)(m0 + q) * A.bmax + ray] = hv[q];
+      }
+    }
+  }
+}
+
+// MODE 0: raw outputs for raw features; 1: decoded camera image + fallback
+// list; 2: training forward (raw outputs, pre-activations and transposed
+// activations saved).
+template <int MODE>
+__global__ void __launch_bounds__(64) k_mlp_fwd(FwdArgs A) {
+  __shared__ __attribute__((aligned(16))) __bf16 act[RAYS * LDA];
+  const int lane = threadIdx.x, r = lane & 31, half = lane >> 5;
+  const int64_t ray = (int64_t)blockIdx.x * RAYS + r;
+  const bool valid = ray < A.m;
+
+  float f[4] = {0.f, 0.f, 0.f, 0.f};
+  if (valid) {
+    if (MODE == 1) {
+      const int64_t row = ray / A.cam.width, col = ray % A.cam.width;
+      const float al = (float)(A.cam.alpha_min + (col + 0.5) * (A.cam.alpha_max - A.cam.alpha_min) / A.cam.width);
+      const float be = (float)(A.cam.beta_min + (row + 0.5) * (A.cam.beta_max - A.cam.beta_min) / A.cam.height);
+      norm_features(al, be, (float)A.cam.a, (float)A.cam.incl, f);
+    } else {
+      const f32x4 xv = *reinterpret_cast<const f32x4*>(A.x + ray * 4);
+      norm_features(xv[0], xv[1], xv[2], xv[3], f);
+    }
+  }
+  // layer 0 (K = 4 padded to 16): B operand = features, rows 8 * half + j
+  bf16x8 bx;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) bx[j] = (half == 0 && j < 4) ? (__bf16)f[j] : (__bf16)0.0f;
+  if (MODE == 2 && valid) {
+    __bf16* ht0 = ht_layer(A.ht, 0, A.bmax);
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      ht0[(int64_t)(16 * half + j) * A.bmax + ray] = (half == 0 && j < 4) ? (__bf16)f[j & 3] : (__bf16)0.0f;
+  }
+  f32x16 acc[8];
+  const f32x16 zero = {};
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[0] + (t * 32 + r) * KPAD[0] + 8 * half);
+    acc[t] = mfma(aw, bx, zero);
+  }
+  store_hidden<MODE>(A, 0, acc, act, r, half, ray, valid);
+
+  // hidden layers 1..3 (256 -> 256)
+  for (int l = 1; l < 4; ++l) {
+    wave_sync();
+    const __bf16* w = A.wb + (l == 1 ? OFF_WB[1] : l == 2 ? OFF_WB[2] : OFF_WB[3]);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = zero;
+    for (int ks = 0; ks < HID / 16; ++ks) {
+      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(act + r * LDA + ks * 16 + 8 * half);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const bf16x8 aw = *reinterpret_cast<const bf16x8*>(w + (t * 32 + r) * HID + ks * 16 + 8 * half);
+        acc[t] = mfma(aw, bv, acc[t]);
+      }
+    }
+    wave_sync();
+    store_hidden<MODE>(A, l, acc, act, r, half, ray, valid);
+  }
+
+  // output layer (256 -> 4, padded to 32 rows)
+  wave_sync();
+  f32x16 o = zero;
+  for (int ks = 0; ks < HID / 16; ++ks) {
+    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(act + r * LDA + ks * 16 + 8 * half);
+    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + r * HID + ks * 16 + 8 * half);
+    o = mfma(aw, bv, o);
+  }
+  // outputs 0..3 of ray r sit in elements 0..3 of lane r (half 0)
+  bool unsure = false;
+  if (half == 0 && valid) {
+    const float* b4 = A.params + OFF_B[4];
+    f32x4 y;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) y[q] = o[q] + b4[q];
+    if (MODE == 1) {
+      const float p = sigmoidf(y[3]);
+      f32x4 d;
+      d[0] = __expf(2.0f * y[0] + 2.0f);
+      d[1] = 3.14159265358979f * y[1];
+      d[2] = 0.3f * y[2] + 0.8f;
+      d[3] = p;
+      *reinterpret_cast<f32x4*>(A.y + ray * 4) = d;
+      unsure = p > A.tau && p < 1.0f - A.tau;
+    } else {
+      *reinterpret_cast<f32x4*>(A.y + ray * 4) = y;
+    }
+  }
+  if (MODE == 1) {
+    // wave-aggregated append of the uncertain pixels
+    const unsigned long long mask = __ballot(unsure);
+    if (mask) {
+      const int leader = __ffsll((long long)mask) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(A.fb_count, __popcll(mask));
+      base = __shfl(base, leader);
+      if (unsure) {
+        const unsigned rank =
+            __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+        A.fb_ids[base + rank] = (int32_t)ray;
+      }
+    }
+  }
+}
+
+// Loss and its gradient with respect to the raw outputs; dz [bmax][32] and
+// dzT [32][bmax] (BF16, columns / rows 4..31 zero).
+__global__ void k_mlp_loss(const float* y, const float* t, const uint8_t* mask, int64_t b, __bf16* dz, __bf16* dzT,
+                           int64_t bmax, float* loss) {
+  __shared__ float part[4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.0f;
+  if (i < b) {
+    const f32x4 yv = *reinterpret_cast<const f32x4*>(y + i * 4);
+    const f32x4 tv = *reinterpret_cast<const f32x4*>(t + i * 4);
+    const int mk = mask[i];
+    const float inv = 1.0f / (float)b;
+    const float e0 = (mk & 1) ? yv[0] - tv[0] : 0.0f;
+    const float e1 = (mk & 1) ? yv[1] - tv[1] : 0.0f;
+    const float e2 = (mk & 2) ? yv[2] - tv[2] : 0.0f;
+    const float s = sigmoidf(yv[3]);
+    const float bce = fmaxf(yv[3], 0.0f) - yv[3] * tv[3] + log1pf(__expf(-fabsf(yv[3])));
+    l = e0 * e0 + e1 * e1 + e2 * e2 + bce;
+    const float d[4] = {2.0f * e0 * inv, 2.0f * e1 * inv, 2.0f * e2 * inv, (s - tv[3]) * inv};
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+      const __bf16 v = (__bf16)(c < 4 ? d[c] : 0.0f);
+      dz[i * 32 + c] = v;
+      dzT[(int64_t)c * bmax + i] = v;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_down(l, off);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.0f;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
+    atomicAdd(loss, s / (float)b);
+  }
+}
+
+// Gradient with respect to a layer's input, times SiLU' of the layer below:
+// dz_out[ray][k] = (sum_o dz[ray][o] W[o][k]) * silu'(zprev[ray][k]).
+__global__ void __launch_bounds__(64) k_mlp_bwd_dx(const __bf16* wbt, int opad, const __bf16* dz, const float* zprev,
+                                                    __bf16* dz_out, __bf16* dzT_out, int64_t bmax) {
+  const int lane = threadIdx.x, r = lane & 31, half = lane >> 5;
+  const int64_t ray = (int64_t)blockIdx.x * RAYS + r;
+  f32x16 acc[8];
+  const f32x16 zero = {};
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc[t] = zero;
+  for (int os = 0; os < opad / 16; ++os) {
+    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(dz + ray * opad + os * 16 + 8 * half);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const bf16x8 aw = *reinterpret_cast<const bf16x8*>(wbt + (t * 32 + r) * opad + os * 16 + 8 * half);
+      acc[t] = mfma(aw, bv, acc[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int k0 = t * 32 + 8 * g + 4 * half;
+      const f32x4 zz = *reinterpret_cast<const f32x4*>(zprev + ray * HID + k0);
+      bf16x4 dv;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dv[q] = (__bf16)(acc[t][4 * g + q] * dsilu(zz[q]));
+      *reinterpret_cast<bf16x4*>(dz_out + ray * HID + k0) = dv;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dzT_out[(int64_t)(k0 + q) * bmax + ray] = dv[q];
+    }
+  }
+}
+
+// Split-batch partial weight and bias gradients of one layer:
+// part[s][W_l + o * nin + i] = sum over split s of dz[b][o] h[b][i],
+// part[s][b_l + o] = sum over split s of dz[b][o].
+__global__ void __launch_bounds__(64) k_mlp_bwd_dw(const __bf16* dzT, int opad, int nout, const __bf16* ht, int ipad,
+                                                    int nin, int64_t bmax, int64_t b, float* part, int off_w,
+                                                    int off_b) {
+  const int lane = threadIdx.x, r = lane & 31, half = lane >> 5;
+  const int tiles_i = ipad / 32;
+  const int ot = blockIdx.x / tiles_i, it = blockIdx.x % tiles_i;
+  const int s = blockIdx.y;
+  const int64_t per = b / SPLITS;
+  const int64_t b0 = s * per, b1 = b0 + per;
+  f32x16 acc = {};
+  for (int64_t kb = b0; kb < b1; kb += 16) {
+    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(dzT + (int64_t)(ot * 32 + r) * bmax + kb + 8 * half);
+    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(ht + (int64_t)(it * 32 + r) * bmax + kb + 8 * half);
+    acc = mfma(aw, bv, acc);
+  }
+  float* ps = part + (int64_t)s * NP;
+  const int i = it * 32 + r;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int o = ot * 32 + 8 * (e / 4) + 4 * half + (e % 4);
+    if (o < nout && i < nin) ps[off_w + o * nin + i] = acc[e];
+  }
+  if (it == 0) {
+    const int o = ot * 32 + r;
+    const int64_t mid = b0 + per / 2;
+    float sb = 0.0f;
+    for (int64_t kb = half ? mid : b0; kb < (half ? b1 : mid); ++kb) sb += (float)dzT[(int64_t)o * bmax + kb];
+    sb += __shfl_down(sb, 32);
+    if (half == 0 && o < nout) ps[off_b + o] = sb;
+  }
+}
+
+__device__ inline int layer_of(int p) {
+  return p < 1280 ? 0 : p < 67072 ? 1 : p < 132864 ? 2 : p < 198656 ? 3 : 4;
+}
+
+// BF16 copies of one FP32 weight (biases have none).
+__device__ inline void write_bf16(int p, float w, __bf16* wb, __bf16* wbt) {
+  const int l = layer_of(p);
+  const int rel = p - OFF_W[l];
+  const int nin = l == 0 ? 4 : 256;
+  const int nw = (l == 0 || l == 4) ? 1024 : 65536;
+  if (rel >= nw) return;  // a bias
+  const int o = rel / nin, i = rel % nin;
+  const int kpad = l == 0 ? 16 : 256;
+  const int offwb = l == 0 ? 0 : l == 1 ? 4096 : l == 2 ? 69632 : l == 3 ? 135168 : 200704;
+  wb[offwb + o * kpad + i] = (__bf16)w;
+  if (wbt && l >= 1) {
+    const int mpad = l == 4 ? 32 : 256;
+    const int offwbt = (l - 1) * 65536;
+    wbt[offwbt + i * mpad + o] = (__bf16)w;
+  }
+}
+
+__global__ void k_zero_i32(int32_t* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
+__global__ void k_mlp_fill_bf16(__bf16* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (__bf16)0.0f;
+}
+
+__global__ void k_mlp_sync(const float* params, __bf16* wb, __bf16* wbt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < NP) write_bf16(p, params[p], wb, wbt);
+}
+
+__global__ void k_mlp_reduce(const float* part, float* grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NP) return;
+  float g = 0.0f;
+  for (int s = 0; s < SPLITS; ++s) g += part[(int64_t)s * NP + p];
+  grad[p] = g;
+}
+
+__global__ void k_mlp_adam(float* params, float* m, float* v, const float* part, kh_adam opt, __bf16* wb,
+                           __bf16* wbt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NP) return;
+  float g = 0.0f;
+  for (int s = 0; s < SPLITS; ++s) g += part[(int64_t)s * NP + p];
+  const float mm = opt.beta1 * m[p] + (1.0f - opt.beta1) * g;
+  const float vv = opt.beta2 * v[p] + (1.0f - opt.beta2) * g * g;
+  m[p] = mm;
+  v[p] = vv;
+  const float c1 = 1.0f - powf(opt.beta1, (float)opt.step);
+  const float c2 = 1.0f - powf(opt.beta2, (float)opt.step);
+  const float w = params[p] - opt.lr * (mm / c1) / (sqrtf(vv / c2) + opt.eps);
+  params[p] = w;
+  write_bf16(p, w, wb, wbt);
+}
+
+// Training data from an integrated state.
+__global__ void k_mlp_targets(KState S, const double* alpha, const double* beta, const double* spin,
+                              const double* incl, float* x, float* t, uint8_t* mask) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  f32x4 xv;
+  xv[0] = (float)alpha[i];
+  xv[1] = (float)beta[i];
+  xv[2] = (float)spin[i];
+  xv[3] = (float)incl[i];
+  *reinterpret_cast<f32x4*>(x + i * 4) = xv;
+  const bool cross = S.n_cross && S.n_cross[i] > 0 && S.k_cross > 0;
+  const double r = cross ? S.cross[i * 3 * S.k_cross + 0] : 0.0;
+  const double phi = cross ? S.cross[i * 3 * S.k_cross + 1] : 0.0;
+  const double g = cross ? S.cross[i * 3 * S.k_cross + 2] : 0.0;
+  const bool rok = cross && r > 0.0 && isfinite(r) && isfinite(phi);
+  const bool gok = rok && isfinite(g);
+  f32x4 tv;
+  tv[0] = rok ? (float)((log(r) - 2.0) * 0.5) : 0.0f;
+  tv[1] = rok ? (float)(phi / M_PI) : 0.0f;
+  tv[2] = gok ? (float)((g - 0.8) / 0.3) : 0.0f;
+  tv[3] = S.status[i] == KH_CAPTURED ? 1.0f : 0.0f;
+  *reinterpret_cast<f32x4*>(t + i * 4) = tv;
+  mask[i] = (uint8_t)((rok ? 1 : 0) | (gok ? 2 : 0));
+}
+
+__global__ void k_image_from_state(KState S, const int32_t* pix, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  const int64_t p = pix ? pix[i] : i;
+  const bool cross = S.n_cross && S.n_cross[i] > 0 && S.k_cross > 0;
+  f32x4 v;
+  v[0] = cross ? (float)S.cross[i * 3 * S.k_cross + 0] : __builtin_nanf("");
+  v[1] = cross ? (float)S.cross[i * 3 * S.k_cross + 1] : __builtin_nanf("");
+  v[2] = cross ? (float)S.cross[i * 3 * S.k_cross + 2] : __builtin_nanf("");
+  v[3] = S.status[i] == KH_CAPTURED ? 1.0f : 0.0f;
+  *reinterpret_cast<f32x4*>(out + p * 4) = v;
+}
+
+// Workspace carving (bytes, 256-aligned pieces).
+struct Work {
+  float* y;
+  float* z;
+  __bf16* ht;
+  __bf16 *dz_a, *dz_b, *dz4;
+  __bf16 *dzT_a, *dzT_b, *dz4T;
+  float* part;
+};
+
+int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+Work carve(void* base, int64_t bmax, int64_t* total) {
+  char* p = static_cast<char*>(base);
+  int64_t off = 0;
+  Work w{};
+  auto take = [&](int64_t bytes) {
+    char* q = p ? p + off : nullptr;
+    off += align256(bytes);
+    return q;
+  };
+  w.y = reinterpret_cast<float*>(take(bmax * 4 * 4));
+  w.z = reinterpret_cast<float*>(take(4 * bmax * HID * 4));
+  w.ht = reinterpret_cast<__bf16*>(take((HT0_ROWS + 4 * HID) * bmax * 2));
+  w.dz_a = reinterpret_cast<__bf16*>(take(bmax * HID * 2));
+  w.dz_b = reinterpret_cast<__bf16*>(take(bmax * HID * 2));
+  w.dz4 = reinterpret_cast<__bf16*>(take(bmax * 32 * 2));
+  w.dzT_a = reinterpret_cast<__bf16*>(take(bmax * HID * 2));
+  w.dzT_b = reinterpret_cast<__bf16*>(take(bmax * HID * 2));
+  w.dz4T = reinterpret_cast<__bf16*>(take(bmax * 32 * 2));
+  w.part = reinterpret_cast<float*>(take((int64_t)SPLITS * NP * 4));
+  if (total) *total = off;
+  return w;
+}
+
+kh_status check_net(kh_ctx* ctx, const kh_mlp* net, bool train) {
+  if (!net || !net->params || !net->wb) return fail(ctx, KH_EINVAL, "network params and wb are required");
+  if (!aligned(net->params, 16) || !aligned(net->wb, 16) || !device_ok(net->params) || !device_ok(net->wb))
+    return fail(ctx, KH_EINVAL, "network arrays must be 16-byte aligned device memory");
+  if (train) {
+    const void* ps[] = {net->adam_m, net->adam_v, net->wbt};
+    for (const void* q : ps)
+      if (!q || !aligned(q, 16) || !device_ok(q))
+        return fail(ctx, KH_EINVAL, "training needs adam_m, adam_v and wbt (16-byte aligned device memory)");
+  }
+  return KH_OK;
+}
+
+// Shared body of kh_mlp_grad and kh_mlp_train_step.
+kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batch, const float* x, const float* t,
+                    const uint8_t* mask, int32_t b, float* loss, hipStream_t strm, Work* out_w) {
+  if (max_batch < 256 || max_batch % 256) return fail(ctx, KH_EINVAL, "max_batch must be a positive multiple of 256");
+  if (b < 256 || b % 256 || b > max_batch) return fail(ctx, KH_EINVAL, "b must be a multiple of 256 <= max_batch");
+  const void* ins[] = {x, t, mask, loss, work};
+  for (const void* q : ins)
+    if (!q || !device_ok(q)) return fail(ctx, KH_EINVAL, "x, t, mask, loss and work must be device memory");
+  if (!aligned(x, 16) || !aligned(t, 16) || !aligned(work, 256))
+    return fail(ctx, KH_EINVAL, "x, t must be 16-byte aligned and work 256-byte aligned");
+  const int64_t bmax = max_batch;
+  Work w = carve(work, bmax, nullptr);
+  *out_w = w;
+  FwdArgs A{};
+  A.params = net->params;
+  A.wb = reinterpret_cast<const __bf16*>(net->wb);
+  A.x = x;
+  A.m = b;
+  A.y = w.y;
+  A.z = w.z;
+  A.ht = w.ht;
+  A.bmax = bmax;
+  hipLaunchKernelGGL(k_mlp_fwd<2>, dim3((unsigned)(b / RAYS)), dim3(64), 0, strm, A);
+  hipLaunchKernelGGL(k_mlp_loss, dim3((unsigned)(b / 256)), dim3(256), 0, strm, w.y, t, mask, (int64_t)b, w.dz4,
+                     w.dz4T, bmax, loss);
+  const __bf16* wbt = reinterpret_cast<const __bf16*>(net->wbt);
+  auto ht = [&](int l) { return ht_layer(w.ht, l, bmax); };
+  auto zl = [&](int l) { return w.z + (int64_t)l * bmax * HID; };
+  const dim3 gdx((unsigned)(b / RAYS));
+  // layer 4
+  hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(1 * 8, SPLITS), dim3(64), 0, strm, w.dz4T, 32, 4, ht(4), 256, 256, bmax,
+                     (int64_t)b, w.part, h_OFF_W[4], h_OFF_B[4]);
+  hipLaunchKernelGGL(k_mlp_bwd_dx, gdx, dim3(64), 0, strm, wbt + OFF_WBT[4], 32, w.dz4, zl(3), w.dz_a, w.dzT_a, bmax);
+  // layers 3, 2, 1
+  __bf16* cur = w.dz_a;
+  __bf16* curT = w.dzT_a;
+  __bf16* nxt = w.dz_b;
+  __bf16* nxtT = w.dzT_b;
+  for (int l = 3; l >= 1; --l) {
+    hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(8 * 8, SPLITS), dim3(64), 0, strm, curT, 256, 256, ht(l), 256, 256, bmax,
+                       (int64_t)b, w.part, h_OFF_W[l], h_OFF_B[l]);
+    hipLaunchKernelGGL(k_mlp_bwd_dx, gdx, dim3(64), 0, strm, wbt + OFF_WBT[l], 256, cur, zl(l - 1), nxt, nxtT, bmax);
+    std::swap(cur, nxt);
+    std::swap(curT, nxtT);
+  }
+  // layer 0 (inputs padded to one 32-row tile)
+  hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(8 * 1, SPLITS), dim3(64), 0, strm, curT, 256, 256, ht(0), 32, 4, bmax,
+                     (int64_t)b, w.part, h_OFF_W[0], h_OFF_B[0]);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t kh_mlp_work_bytes(int32_t max_batch) {
+  if (max_batch < 256 || max_batch % 256) return -1;
+  int64_t total = 0;
+  carve(nullptr, max_batch, &total);
+  return total;
+}
+
+kh_status kh_mlp_sync(kh_ctx* ctx, const kh_mlp* net, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = false;
+  kh_status s = check_net(ctx, net, false);
+  if (s != KH_OK) return s;
+  if (net->wbt && (!aligned(net->wbt, 16) || !device_ok(net->wbt)))
+    return fail(ctx, KH_EINVAL, "wbt must be NULL or 16-byte aligned device memory");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  hipStream_t strm = (hipStream_t)stream;
+  __bf16* wb = reinterpret_cast<__bf16*>(net->wb);
+  __bf16* wbt = reinterpret_cast<__bf16*>(net->wbt);
+  hipLaunchKernelGGL(k_mlp_fill_bf16, dim3((KH_MLP_WB_ELEMS + 255) / 256), dim3(256), 0, strm, wb,
+                     (int64_t)KH_MLP_WB_ELEMS);
+  if (wbt)
+    hipLaunchKernelGGL(k_mlp_fill_bf16, dim3((KH_MLP_WBT_ELEMS + 255) / 256), dim3(256), 0, strm, wbt,
+                       (int64_t)KH_MLP_WBT_ELEMS);
+  hipLaunchKernelGGL(k_mlp_sync, dim3((NP + 255) / 256), dim3(256), 0, strm, net->params, wb, wbt);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+kh_status kh_mlp_forward(kh_ctx* ctx, const kh_mlp* net, const float* x, float* y, int64_t m, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = capturing(stream);
+  kh_status s = check_net(ctx, net, false);
+  if (s != KH_OK) return s;
+  if (m < 1 || m >= (int64_t(1) << 31)) return fail(ctx, KH_EINVAL, "m must be in [1, 2^31)");
+  if (!x || !y || !aligned(x, 16) || !aligned(y, 16) || !device_ok(x) || !device_ok(y))
+    return fail(ctx, KH_EINVAL, "x and y must be 16-byte aligned device arrays [m][4]");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  FwdArgs A{};
+  A.params = net->params;
+  A.wb = reinterpret_cast<const __bf16*>(net->wb);
+  A.x = x;
+  A.m = m;
+  A.y = y;
+  hipLaunchKernelGGL(k_mlp_fwd<0>, dim3((unsigned)((m + RAYS - 1) / RAYS)), dim3(64), 0, (hipStream_t)stream, A);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+kh_status kh_mlp_image(kh_ctx* ctx, const kh_mlp* net, const kh_camera* cam, float tau, float* out,
+                       int32_t* fallback_ids, int32_t* fallback_count, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = capturing(stream);
+  kh_status s = check_net(ctx, net, false);
+  if (s != KH_OK) return s;
+  if (!cam || cam->width < 1 || cam->height < 1 || !(std::fabs(cam->a) <= 1.0))
+    return fail(ctx, KH_EINVAL, "camera: need width, height >= 1 and |a| <= 1");
+  const int64_t m = int64_t(cam->width) * cam->height;
+  if (m >= (int64_t(1) << 31)) return fail(ctx, KH_EINVAL, "image too large");
+  if (!(tau >= 0.0f && tau < 0.5f)) return fail(ctx, KH_EINVAL, "tau must be in [0, 0.5)");
+  const void* ps[] = {out, fallback_ids, fallback_count};
+  for (const void* q : ps)
+    if (!q || !device_ok(q)) return fail(ctx, KH_EINVAL, "out, fallback_ids, fallback_count must be device memory");
+  if (!aligned(out, 16)) return fail(ctx, KH_EINVAL, "out must be 16-byte aligned");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  hipStream_t strm = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, strm, fallback_count);
+  FwdArgs A{};
+  A.params = net->params;
+  A.wb = reinterpret_cast<const __bf16*>(net->wb);
+  A.m = m;
+  A.cam = *cam;
+  A.y = out;
+  A.tau = tau;
+  A.fb_ids = fallback_ids;
+  A.fb_count = fallback_count;
+  hipLaunchKernelGGL(k_mlp_fwd<1>, dim3((unsigned)((m + RAYS - 1) / RAYS)), dim3(64), 0, strm, A);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+kh_status kh_mlp_targets(kh_ctx* ctx, const kh_state* st, const double* alpha, const double* beta,
+                         const double* spin, const double* incl, float* x, float* t, uint8_t* mask, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = false;
+  kh_status s = check_state(ctx, st, false);
+  if (s != KH_OK) return s;
+  const void* ps[] = {alpha, beta, spin, incl, x, t, mask};
+  for (const void* q : ps)
+    if (!q || !device_ok(q)) return fail(ctx, KH_EINVAL, "alpha, beta, spin, incl, x, t, mask must be device memory");
+  if (!aligned(x, 16) || !aligned(t, 16)) return fail(ctx, KH_EINVAL, "x and t must be 16-byte aligned");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  const KState ks = to_k(st);
+  hipLaunchKernelGGL(k_mlp_targets, dim3((unsigned)((st->n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, ks,
+                     alpha, beta, spin, incl, x, t, mask);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+kh_status kh_mlp_grad(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batch, const float* x, const float* t,
+                      const uint8_t* mask, int32_t b, float* grad, float* loss, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = capturing(stream);
+  kh_status s = check_net(ctx, net, false);
+  if (s != KH_OK) return s;
+  if (!net->wbt || !device_ok(net->wbt)) return fail(ctx, KH_EINVAL, "gradients need wbt");
+  if (!grad || !aligned(grad, 16) || !device_ok(grad)) return fail(ctx, KH_EINVAL, "grad must be device memory");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  hipStream_t strm = (hipStream_t)stream;
+  Work w;
+  if ((s = grad_pass(ctx, net, work, max_batch, x, t, mask, b, loss, strm, &w)) != KH_OK) return s;
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((NP + 255) / 256), dim3(256), 0, strm, w.part, grad);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+kh_status kh_mlp_train_step(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batch, const float* x,
+                            const float* t, const uint8_t* mask, int32_t b, const kh_adam* opt, float* loss,
+                            void* stream) {
+  if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = capturing(stream);
+  kh_status s = check_net(ctx, net, true);
+  if (s != KH_OK) return s;
+  if (!opt || !(opt->lr > 0.0f) || opt->step < 1) return fail(ctx, KH_EINVAL, "need lr > 0 and step >= 1");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  hipStream_t strm = (hipStream_t)stream;
+  Work w;
+  if ((s = grad_pass(ctx, net, work, max_batch, x, t, mask, b, loss, strm, &w)) != KH_OK) return s;
+  hipLaunchKernelGGL(k_mlp_adam, dim3((NP + 255) / 256), dim3(256), 0, strm, net->params, net->adam_m, net->adam_v,
+                     w.part, *opt, reinterpret_cast<__bf16*>(net->wb), reinterpret_cast<__bf16*>(net->wbt));
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+kh_status kh_image_from_state(kh_ctx* ctx, const kh_state* st, const int32_t* pix, float* out, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = capturing(stream);
+  kh_status s = check_state(ctx, st, false);
+  if (s != KH_OK) return s;
+  if (!out || !aligned(out, 16) || !device_ok(out)) return fail(ctx, KH_EINVAL, "out must be device memory");
+  if (pix && !device_ok(pix)) return fail(ctx, KH_EINVAL, "pix must be NULL or device memory");
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  const KState ks = to_k(st);
+  hipLaunchKernelGGL(k_image_from_state, dim3((unsigned)((st->n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     ks, pix, out);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+"""GPU: the surrogate network's BF16-MFMA kernels against the FP64 numpy
+reference, and a small end-to-end training + fallback run."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1706_07062_amd as K
+from oracle import mlp as M
+from paper_1706_07062_amd import surrogate as S
+from paper_1706_07062_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch.cuda.set_device(0)
+    c = K.Context(0)
+    yield c
+    c.close()
+
+
+rng = np.random.default_rng(1706070627)
+
+
+def _batch(n):
+    x = np.stack([rng.uniform(-12, 12, n), rng.uniform(-12, 12, n), rng.uniform(0, 0.998, n),
+                  np.radians(rng.uniform(5, 85, n))], axis=1).astype(np.float32)
+    t = np.stack([rng.normal(size=n), rng.normal(size=n), rng.normal(size=n), (rng.random(n) < 0.3) * 1.0],
+                 axis=1).astype(np.float32)
+    mask = rng.integers(0, 4, n).astype(np.uint8)
+    return x, t, mask
+
+
+def test_forward_matches_reference(ctx):
+    """Raw outputs for 1000 rays (31 full waves and a ragged one) equal the FP64
+    reference with BF16 storage of weights and activations, to the FP32
+    accumulation-order level."""
+    say("mlp forward")
+    p = S.init_params(11)
+    p[M.NPARAMS - 4:] = [0.1, -0.2, 0.3, 0.05]  # nonzero output bias
+    net = K.Mlp(p, train=False)
+    ctx.kh_mlp_sync(net)
+    x, _, _ = _batch(1000)
+    y = torch.empty((1000, 4), dtype=torch.float32, device="cuda")
+    ctx.kh_mlp_forward(net, torch.from_numpy(x).cuda(), y)
+    got = y.cpu().numpy()
+    want, _ = M.forward(p.astype(np.float64), x.astype(np.float64), bf16_storage=True)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    say(f"  max abs err / max |y| = {err:.2e}")
+    assert err < 2e-2
+    # and the plain FP64 network is close too (BF16 storage costs ~1e-2)
+    plain, _ = M.forward(p.astype(np.float64), x.astype(np.float64))
+    assert np.abs(got - plain).max() / np.abs(plain).max() < 5e-2
+
+
+def test_gradient_matches_reference(ctx):
+    """kh_mlp_grad on a 512-ray batch against the FP64 reference gradient
+    (BF16 storage of weights and activations; the GPU also stores the
+    back-propagated errors as BF16)."""
+    say("mlp gradient")
+    p = S.init_params(12) * 0.7
+    net = K.Mlp(p, train=True)
+    ctx.kh_mlp_sync(net)
+    x, t, mask = _batch(512)
+    work = torch.empty(K.kh_mlp_work_bytes(512), dtype=torch.uint8, device="cuda")
+    grad = torch.empty(K.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ctx.kh_mlp_grad(net, work, 512, torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(),
+                    torch.from_numpy(mask).cuda(), 512, grad, loss)
+    g = grad.cpu().numpy().astype(np.float64)
+    lw, gw = M.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64), mask,
+                             bf16_storage=True)
+    rel = np.linalg.norm(g - gw) / np.linalg.norm(gw)
+    cos = g @ gw / (np.linalg.norm(g) * np.linalg.norm(gw))
+    say(f"  loss {loss.item():.6f} vs {lw:.6f}; grad rel err {rel:.2e}, cosine {cos:.6f}")
+    assert loss.item() == pytest.approx(lw, rel=1e-2)
+    assert rel < 3e-2 and cos > 0.9995
+    # every layer's weight and bias block agrees in direction
+    off = 0
+    for nin, nout in M.LAYERS:
+        for size in (nin * nout, nout):
+            a, b = g[off:off + size], gw[off:off + size]
+            if np.linalg.norm(b) > 0:
+                assert a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300) > 0.995, (nin, nout, size)
+            off += size
+
+
+def test_training_and_fallback_image(ctx):
+    """Train on 2^18 integrated rays for 600 steps, then render a 256x256 image
+    at a = 0.9, i = 45 deg: the loss falls, the fallback integrates a minority
+    of pixels, and the merged image's capture map matches the integrator's."""
+    say("surrogate small end-to-end")
+    sur = S.Surrogate(ctx, seed=1, max_batch=4096)
+    x, t, mask, t_data = sur.make_data(1 << 18)
+    m = mask.cpu().numpy()
+    assert (m & 1).mean() > 0.5
+    hist = sur.train(x, t, mask, steps=600, batch=4096, lr=2e-3, log_every=100)
+    say(f"  data {t_data:.2f} s; loss history {[round(v, 4) for _, v in hist]}")
+    assert hist[-1][1] < 0.5 * hist[0][1]
+    cam = W.surrogate_eval_camera(side=256)
+    ref, _ = S.integrate_image(ctx, cam)
+    img, tm = sur.render(cam, tau=0.02)
+    err = S.image_error(img, ref)
+    say(f"  fallback fraction {tm['fallback_fraction']:.3f}; error {err}")
+    assert tm["fallback_fraction"] < 0.6
+    assert err["capture_mismatch"] < 0.02

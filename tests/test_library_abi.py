@@ -7,12 +7,12 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "kerrhip.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("kerrhip.h", "kerrhip_mlp.h")]
 LIB = os.path.join(ROOT, "paper_1706_07062_amd", "libkerrhip.so")
 
 
 def declared_symbols():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(kh_[a-z_0-9]+)\s*\(", text)))
 
@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 def test_binding_covers_every_declared_symbol():
     import paper_1706_07062_amd as K
 
-    assert sorted(K.EXPORTS) == declared_symbols()
+    assert sorted(K.EXPORTS + K.MLP_EXPORTS) == declared_symbols()
 
 
 def test_default_params_and_struct_layout():
