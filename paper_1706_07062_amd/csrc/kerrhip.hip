@@ -35,6 +35,8 @@ static_assert(sizeof(kh_state) == 120, "kh_state layout");
 namespace {
 
 constexpr int kQueueSlots = 16;  // work-queue counters per context
+// Status flags that live only between the integrate kernel and its finalize pass.
+constexpr int kRetired = 0x100, kPhiPending = 0x200, kStatusMask = 0xff;
 constexpr int kParts = 8;        // ray-range partitions = XCDs of an MI355X
 
 __device__ inline double hscale(int kind, double r) { return kind == KH_TIMELIKE ? r * sqrt(r) : r; }
@@ -44,25 +46,24 @@ __device__ inline double r_horizon(double a) {
   return 1.0 + sqrt(q > 0.0 ? q : 0.0);
 }
 
-// Growth / shrink factors of the step-size controller.
+// Growth / shrink factors of the step-size controller from raw = 0.9 err^{-1/5},
+// computed once per attempt before the accept / reject branch.
 template <typename T>
-__device__ inline T grow_factor(T err, bool after_reject) {
+__device__ inline T grow_factor(T err, T raw, bool after_reject) {
   T fac;
   if (err == T(0))
     fac = T(5);
   else {
-    fac = T(0.9) * pow(err, T(-0.2));
-    fac = fac < T(0.2) ? T(0.2) : fac;
+    fac = raw < T(0.2) ? T(0.2) : raw;
     fac = fac > T(5) ? T(5) : fac;
   }
   if (after_reject && fac > T(1)) fac = T(1);
   return fac;
 }
 template <typename T>
-__device__ inline T shrink_factor(T err) {
+__device__ inline T shrink_factor(T err, T raw) {
   if (err != err) return T(0.2);
-  const T fac = T(0.9) * pow(err, T(-0.2));
-  return fac < T(0.2) ? T(0.2) : fac;
+  return raw < T(0.2) ? T(0.2) : raw;
 }
 
 // ---------------------------------------------------------------------------
@@ -309,6 +310,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
       else
         err = dp5_attempt<FORM, TS, TS>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
 
+      const TS raw = TS(0.9) * pow(err, TS(-0.2));
       if (err <= TS(1)) {
         ++nacc;
         ++steps;
@@ -384,7 +386,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
         r_cur = r_new;
         rdot_cur = rdot_new;
         if (status == KH_ACTIVE) {
-          h = h * (double)grow_factor<TS>(err, after_reject);
+          h = h * (double)grow_factor<TS>(err, raw, after_reject);
           const double hm = P.hmax_coeff * hscale(kind, (double)r_cur);
           h = h < hm ? h : hm;
           after_reject = false;
@@ -392,7 +394,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
         }
       } else {
         ++nrej;
-        h = h * (double)shrink_factor<TS>(err);
+        h = h * (double)shrink_factor<TS>(err, raw);
         after_reject = true;
         // written so that a NaN step size also ends the ray
         if (!(h >= 1e-12 * P.h_coeff * hscale(kind, (double)r_cur))) status = KH_FAILED;
@@ -409,8 +411,9 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
       }
       S.h[ray] = h;
       S.lam[ray] = lam;
-      S.phi[ray] = (P.k_cross > 0) ? atan2((double)x[2], (double)x[1]) + (2.0 * M_PI) * wind : phi_in;
-      S.status[ray] = status;
+      // the finalize pass adds atan2(y, x) to the winding part and clears the flags
+      S.phi[ray] = (P.k_cross > 0) ? (2.0 * M_PI) * wind : phi_in;
+      S.status[ray] = status | kRetired | (P.k_cross > 0 ? kPhiPending : 0);
       S.n_acc[ray] = nacc;
       S.n_rej[ray] = nrej;
       if (S.n_cross) S.n_cross[ray] = ncross;
@@ -425,23 +428,30 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
   }
 }
 
-// Constants of motion of every ray's current state (after an integrate call),
-// in FP64, fully parallel.  Rays the call skipped keep the same state, so
-// recomputing theirs reproduces the earlier value.
-__global__ void k_constants_end(KState S) {
+// Finalize the rays an integrate call retired (flagged in their status), fully
+// parallel: the unwrapped azimuth's atan2(y, x) term and the constants of
+// motion in FP64 are done here rather than in the divergent retire path.
+__global__ void k_finalize(KState S) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = S.n;
   if (i >= n) return;
-  double x[4], k[4], cst[4];
+  const int st = S.status[i];
+  if (!(st & kRetired)) return;
+  double x[4], k[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     x[c] = S.s[c * n + i];
     k[c] = S.s[(4 + c) * n + i];
   }
-  const double a = S.spin[i];
-  constants(S.kind[i] == KH_NULL ? -a : a, x, k, cst);
+  if (st & kPhiPending) S.phi[i] = S.phi[i] + atan2(x[2], x[1]);
+  if (S.c1) {
+    double cst[4];
+    const double a = S.spin[i];
+    constants(S.kind[i] == KH_NULL ? -a : a, x, k, cst);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) S.c1[q * n + i] = cst[q];
+    for (int q = 0; q < 4; ++q) S.c1[q * n + i] = cst[q];
+  }
+  S.status[i] = st & kStatusMask;
 }
 
 // ---------------------------------------------------------------------------
@@ -1011,9 +1021,9 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   const KState ks = to_k(st);
   void* args[] = {(void*)&kp, (void*)&ks, (void*)&q};
   KH_HIP(ctx, hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, strm));
-  if (st->c1) {
+  {
     const int b = 256;
-    hipLaunchKernelGGL(k_constants_end, dim3((unsigned)((st->n + b - 1) / b)), dim3(b), 0, strm, ks);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((st->n + b - 1) / b)), dim3(b), 0, strm, ks);
     KH_HIP(ctx, hipGetLastError());
   }
   return KH_OK;
