@@ -44,7 +44,7 @@ def kernel_source_hash():
 # HBM bytes per launch of the FP64 DOPRI5 kernel from the committed rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs (profiles/k_integrate_dopri5_fp64_kerr1024.md),
 # valid only for the kernel source they were taken on.
-PROFILED_TRAFFIC = {"source_hash": "70883a54c93a95bb", "bytes": (343502.0625 * 2.0 + 500538.59375 * 1.0) * 1024}
+PROFILED_TRAFFIC = {"source_hash": "fe2015b72478b1ad", "bytes": (119722.1875 * 2.0 + 309763.1875 * 1.0) * 1024}
 
 
 def algorithmic_flops(K, stats, n_rays, method, form):
