@@ -39,19 +39,47 @@ constexpr int kQueueSlots = 16;  // work-queue counters per context
 constexpr int kRetired = 0x100, kPhiPending = 0x200, kStatusMask = 0xff;
 constexpr int kParts = 8;        // ray-range partitions = XCDs of an MI355X
 
-__device__ inline double hscale(int kind, double r) { return kind == KH_TIMELIKE ? r * sqrt(r) : r; }
+__device__ inline double hscale(int kind, double r) { return kind == KH_TIMELIKE ? r * ksqrt(r) : r; }
 
 __device__ inline double r_horizon(double a) {
   const double q = 1.0 - a * a;
   return 1.0 + sqrt(q > 0.0 ? q : 0.0);
 }
 
-// Growth / shrink factors of the step-size controller from raw = 0.9 err^{-1/5},
-// computed once per attempt before the accept / reject branch.
+// q^{-1/10} for the step-size controller, where q = err^2 is the mean square
+// error norm, so the result is err^{-1/5}.  The controller clamps the factor
+// 0.9 err^{-1/5} to [0.2, 5], which only needs q in [3.5e-8, 3.5e6]; q is held
+// to [1e-10, 1e8] (a NaN becomes 1e-10: callers test for it first), which
+// keeps every clamp decision.  An FP32 estimate from the hardware log2 / exp2
+// (relative error ~1e-6) is refined by two Newton steps on y^{-10} = q,
+// y <- y + y (1 - q y^10) / 10, each of which takes the relative error e to
+// about 5.5 e^2: full double precision up to a few ulps, in 17 instructions
+// instead of the ~200 of a general FP64 pow.
+__device__ inline double kpow_m1_10(double q) {
+  q = q > 1e-10 ? q : 1e-10;
+  q = q < 1e8 ? q : 1e8;
+  double y = (double)__builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf((float)q));
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double y2 = y * y, y5 = y2 * y2 * y;
+    const double t = fma(-q, y5 * y5, 1.0);
+    y = fma(0.1 * y, t, y);
+  }
+  return y;
+}
+__device__ inline float kpow_m1_10(float q) {
+  q = q > 1e-10f ? q : 1e-10f;
+  q = q < 1e8f ? q : 1e8f;
+  return __builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf(q));
+}
+
+// Growth / shrink factors of the step-size controller from err2 = err^2 and
+// raw = 0.9 err^{-1/5}, computed once per attempt before the accept / reject
+// branch.
 template <typename T>
-__device__ inline T grow_factor(T err, T raw, bool after_reject) {
+__device__ inline T grow_factor(T err2, T raw, bool after_reject) {
   T fac;
-  if (err == T(0))
+  if (err2 == T(0))
     fac = T(5);
   else {
     fac = raw < T(0.2) ? T(0.2) : raw;
@@ -61,8 +89,8 @@ __device__ inline T grow_factor(T err, T raw, bool after_reject) {
   return fac;
 }
 template <typename T>
-__device__ inline T shrink_factor(T err, T raw) {
-  if (err != err) return T(0.2);
+__device__ inline T shrink_factor(T err2, T raw) {
+  if (err2 != err2) return T(0.2);
   return raw < T(0.2) ? T(0.2) : raw;
 }
 
@@ -304,14 +332,14 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
       TS xn[4], kn[4], a7[4], r_new, rdot_new;
       const TS hs = (TS)h;
       const TS rtol = (TS)P.rtol, atol = (TS)P.atol;
-      TS err;
+      TS err2;  // squared RMS error norm
       if (PREC == KH_PMIXED && __ballot(r_cur < (TS)P.r_fp64) == 0ull)
-        err = dp5_attempt<FORM, TS, TF>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
+        err2 = dp5_attempt<FORM, TS, TF>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
       else
-        err = dp5_attempt<FORM, TS, TS>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
+        err2 = dp5_attempt<FORM, TS, TS>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
 
-      const TS raw = TS(0.9) * pow(err, TS(-0.2));
-      if (err <= TS(1)) {
+      const TS raw = TS(0.9) * kpow_m1_10(err2);
+      if (err2 <= TS(1)) {
         ++nacc;
         ++steps;
         bool bad = false;
@@ -386,7 +414,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
         r_cur = r_new;
         rdot_cur = rdot_new;
         if (status == KH_ACTIVE) {
-          h = h * (double)grow_factor<TS>(err, raw, after_reject);
+          h = h * (double)grow_factor<TS>(err2, raw, after_reject);
           const double hm = P.hmax_coeff * hscale(kind, (double)r_cur);
           h = h < hm ? h : hm;
           after_reject = false;
@@ -394,7 +422,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
         }
       } else {
         ++nrej;
-        h = h * (double)shrink_factor<TS>(err, raw);
+        h = h * (double)shrink_factor<TS>(err2, raw);
         after_reject = true;
         // written so that a NaN step size also ends the ray
         if (!(h >= 1e-12 * P.h_coeff * hscale(kind, (double)r_cur))) status = KH_FAILED;
@@ -642,6 +670,10 @@ inline Cnt krsqrt(Cnt x) {
   return Cnt(1.0 / std::sqrt(x.v));
 }
 inline Cnt krcp(Cnt x) {
+  ++g_tally->div;
+  return Cnt(1.0 / x.v);
+}
+inline Cnt krcp_est(Cnt x) {
   ++g_tally->div;
   return Cnt(1.0 / x.v);
 }

@@ -73,9 +73,22 @@ __host__ __device__ inline float krsqrt(float x) {
   return 1.0f / sqrtf(x);
 #endif
 }
-// sqrt(x) = x / sqrt(x) for x > 0 (0 stays 0).
-__host__ __device__ inline double ksqrt(double x) { return x > 0.0 ? x * krsqrt(x) : x; }
-__host__ __device__ inline float ksqrt(float x) { return x > 0.0f ? x * krsqrt(x) : x; }
+// Reciprocal to about 2^-46 relative (one Newton-Raphson iteration), for the
+// scales of the error norm, which only has to decide err <= 1 and set the
+// next step size.
+__host__ __device__ inline double krcp_est(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+#else
+  return 1.0 / x;
+#endif
+}
+__host__ __device__ inline float krcp_est(float x) { return krcp(x); }
+// sqrt(x) = x / sqrt(x) for x >= 0, without a branch: the argument of the
+// reciprocal square root is kept >= 1e-300 (1e-30 in FP32), so x = 0 gives 0.
+__host__ __device__ inline double ksqrt(double x) { return x * krsqrt(x > 1e-300 ? x : 1e-300); }
+__host__ __device__ inline float ksqrt(float x) { return x * krsqrt(x > 1e-30f ? x : 1e-30f); }
 
 template <typename T>
 struct Accel {

@@ -81,7 +81,12 @@ struct Conv {
 // One Dormand-Prince attempt from (x, k) with acceleration a1 = acc(x, k).
 // State and stage arithmetic in TS; right-hand side evaluated in TR.
 // Outputs the 5th-order state (xn, kn), its acceleration a7 (first stage of
-// the next step), the RMS error norm and the radius / radial rate at (xn, kn).
+// the next step) and the radius / radial rate at (xn, kn); returns the mean
+// square of the scaled error components, i.e. the square of the RMS error
+// norm (the controller needs only err^2 <= 1 and err^{-1/5} = (err^2)^{-1/10}).
+// Coefficients that are exactly zero (A A on the sub-diagonal, b_2, b A on the
+// sixth stage, e_2) are skipped at compile time: IEEE rules forbid the
+// compiler from dropping 0 * s itself.
 template <int FORM, typename TS, typename TR>
 __host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], const TS a1[4], TS h, TS rtol,
                                           TS atol, TS xn[4], TS kn[4], TS a7[4], TS& r_new, TS& rdot_new) {
@@ -96,13 +101,21 @@ __host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], 
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       TS sx = TS(0), sk = TS(0);
+      bool hx = false, hk = false;
 #pragma unroll
       for (int l = 0; l < i; ++l) {
-        sx = sx + TS(DP5.AA[i][l]) * S[l][c];
-        sk = sk + TS(DP5.A[i][l]) * S[l][c];
+        if (DP5.AA[i][l] != 0.0) {
+          sx = hx ? sx + TS(DP5.AA[i][l]) * S[l][c] : TS(DP5.AA[i][l]) * S[l][c];
+          hx = true;
+        }
+        if (DP5.A[i][l] != 0.0) {
+          sk = hk ? sk + TS(DP5.A[i][l]) * S[l][c] : TS(DP5.A[i][l]) * S[l][c];
+          hk = true;
+        }
       }
-      if (c > 0) X[c] = Conv<TS, TR>::to(x[c] + h * (TS(DP5.c[i]) * k[c] + h * sx));
-      K[c] = Conv<TS, TR>::to(k[c] + h * sk);
+      if (c > 0) X[c] = Conv<TS, TR>::to(hx ? x[c] + h * (TS(DP5.c[i]) * k[c] + h * sx)
+                                            : x[c] + h * (TS(DP5.c[i]) * k[c]));
+      K[c] = Conv<TS, TR>::to(hk ? k[c] + h * sk : k[c]);
     }
     const Accel<TR> ra = rhs<FORM, TR>(ac, X, K);
 #pragma unroll
@@ -111,10 +124,17 @@ __host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], 
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     TS sx = TS(0), sk = TS(0);
+    bool hx = false, hk = false;
 #pragma unroll
     for (int l = 0; l < 6; ++l) {
-      sx = sx + TS(DP5.bA[l]) * S[l][c];
-      sk = sk + TS(DP5.b[l]) * S[l][c];
+      if (DP5.bA[l] != 0.0) {
+        sx = hx ? sx + TS(DP5.bA[l]) * S[l][c] : TS(DP5.bA[l]) * S[l][c];
+        hx = true;
+      }
+      if (DP5.b[l] != 0.0) {
+        sk = hk ? sk + TS(DP5.b[l]) * S[l][c] : TS(DP5.b[l]) * S[l][c];
+        hk = true;
+      }
     }
     xn[c] = x[c] + h * (k[c] + h * sx);
     kn[c] = k[c] + h * sk;
@@ -135,20 +155,30 @@ __host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], 
   TS s2 = TS(0);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    TS ex = TS(0), ek = TS(DP5.e[6]) * a7[c];
+    TS ex = TS(0), ek = TS(0);
+    bool hx = false, hk = false;
 #pragma unroll
     for (int l = 0; l < 6; ++l) {
-      ex = ex + TS(DP5.eA[l]) * S[l][c];
-      ek = ek + TS(DP5.e[l]) * S[l][c];
+      if (DP5.eA[l] != 0.0) {
+        ex = hx ? ex + TS(DP5.eA[l]) * S[l][c] : TS(DP5.eA[l]) * S[l][c];
+        hx = true;
+      }
+      if (DP5.e[l] != 0.0) {
+        ek = hk ? ek + TS(DP5.e[l]) * S[l][c] : TS(DP5.e[l]) * S[l][c];
+        hk = true;
+      }
     }
+    // the last-stage term goes last, so the stage values can die before the
+    // final right-hand side is evaluated
+    ek = ek + TS(DP5.e[6]) * a7[c];
     ex = h * h * ex;
     ek = h * ek;
     const TS sx = atol + rtol * kmax(kabs(x[c]), kabs(xn[c]));
     const TS sk = atol + rtol * kmax(kabs(k[c]), kabs(kn[c]));
-    const TS qx = ex * krcp(sx), qk = ek * krcp(sk);
+    const TS qx = ex * krcp_est(sx), qk = ek * krcp_est(sk);
     s2 = s2 + qx * qx + qk * qk;
   }
-  return ksqrt(s2 * TS(0.125));
+  return s2 * TS(0.125);
 }
 
 // One classic RK4 step of length h from (x, k) with acceleration a1 = acc(x, k).

@@ -29,7 +29,7 @@ void host_rhs(int form, int fp32, double a, const double* x, const double* k, do
 void host_dp5(double a, const double* x, const double* k, double h, double rtol, double atol, double* out) {
   kh::Accel<double> r1 = kh::rhs<0, double>(a, x, k);
   double xn[4], kn[4], a7[4], rn, rd;
-  double err = kh::dp5_attempt<0, double, double>(a, x, k, r1.a, h, rtol, atol, xn, kn, a7, rn, rd);
+  double err = std::sqrt(kh::dp5_attempt<0, double, double>(a, x, k, r1.a, h, rtol, atol, xn, kn, a7, rn, rd));
   for (int c = 0; c < 4; ++c) {
     out[c] = xn[c];
     out[4 + c] = kn[c];
