@@ -47,9 +47,10 @@ struct KState {
 
 struct KParams {
   double h_coeff, rtol, atol, hmax_coeff, r_h_factor, r_escape, t_end, r_fp64;
-  int64_t max_steps;
+  int32_t max_steps;  // accepted steps per call (clamped to 2^31 - 1)
+  int32_t max_tries;  // attempts per call before KH_MAX_STEPS (4 max_steps + 1000, clamped)
   int32_t k_cross;
-  int32_t refill_min;
+  int32_t refill_min;  // a wave refills once this many of its lanes are idle
   int32_t parts;  // ray-range partitions of the work queue (1 .. kParts)
 };
 

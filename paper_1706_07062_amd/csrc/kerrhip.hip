@@ -41,10 +41,7 @@ constexpr int kParts = 8;        // ray-range partitions = XCDs of an MI355X
 
 __device__ inline double hscale(int kind, double r) { return kind == KH_TIMELIKE ? r * ksqrt(r) : r; }
 
-__device__ inline double r_horizon(double a) {
-  const double q = 1.0 - a * a;
-  return 1.0 + sqrt(q > 0.0 ? q : 0.0);
-}
+__device__ inline double r_horizon(double a) { return 1.0 + ksqrt(1.0 - a * a); }
 
 // q^{-1/10} for the step-size controller, where q = err^2 is the mean square
 // error norm, so the result is err^{-1/5}.  The controller clamps the factor
@@ -200,13 +197,13 @@ __device__ inline void flush_crossings(double* q, int* qcnt, int count, const KS
 // ---------------------------------------------------------------------------
 // WPE: minimum waves per SIMD the register allocation must allow (1 = no limit).
 template <int METHOD, int PREC, int FORM, int WPE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE < 2 ? 2 : WPE)))
 k_integrate(KParams P, KState S, unsigned long long* qctr) {
   using TS = typename std::conditional<PREC == KH_P32, float, double>::type;  // state / stages
   using TF = typename std::conditional<PREC == KH_P64, double, float>::type;  // fast right-hand side
 
   const int64_t n = S.n;
-  int64_t ray = -1;
+  int ray = -1;  // state.n < 2^31
   // per-wave crossing queue in dynamic LDS (present when crossings are recorded)
   extern __shared__ double kh_lds[];
   const int wave_in_block = threadIdx.x >> 6;
@@ -225,13 +222,12 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
   TS x[4], k[4], a1[4];
   TS r_cur = TS(0), rdot_cur = TS(0);
   TS a_c = TS(0);
-  double a_phys = 0.0, h = 0.0, lam = 0.0, rcap = 0.0;
+  double h = 0.0, lam = 0.0, rcap = 0.0;
   int kind = 0, nacc = 0, nrej = 0, ncross = 0, status = KH_ACTIVE;
   // Unwrapped azimuth = atan2(y, x) + 2 pi * wind: wind counts passages across
   // the negative x axis, so no arctangent is needed on ordinary steps.
   int wind = 0;
-  double phi_in = 0.0;
-  int64_t steps = 0, tries = 0;
+  int steps = 0, tries = 0;  // bounded by max_steps and max_tries (< 2^31)
   bool after_reject = false;
 
   while (true) {
@@ -249,19 +245,19 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
       if (ray < 0 && id >= 0) {
         const int st = S.status[id];
         if (st == KH_ACTIVE || st == KH_MAX_STEPS) {
-          ray = id;
+          ray = (int)id;
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             x[c] = (TS)S.s[c * n + id];
             k[c] = (TS)S.s[(4 + c) * n + id];
           }
           kind = S.kind[id];
-          a_phys = S.spin[id];
+          const double a_phys = S.spin[id];
           a_c = (TS)(kind == KH_NULL ? -a_phys : a_phys);
           h = S.h[id];
           lam = S.lam[id];
-          phi_in = S.phi[id];
-          wind = (int)rint((phi_in - atan2((double)x[2], (double)x[1])) * (0.5 / M_PI));
+          // phi = atan2(y, x) + 2 pi wind on entry; a coarse azimuth recovers wind
+          if (P.k_cross > 0) wind = (int)rint((S.phi[id] - atan2_est((double)x[2], (double)x[1])) * (0.5 / M_PI));
           rcap = P.r_h_factor * r_horizon((double)a_c);
           nacc = S.n_acc[id];
           nrej = S.n_rej[id];
@@ -376,7 +372,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
                 cq[QH * kQCap + j] = h;
                 cq[QAC * kQCap + j] = (double)a_c;
                 cq[QWIND * kQCap + j] = (double)wind0;
-                cq[QTAG * kQCap + j] = (double)(((ray * 8 + ncross) << 1) | (kind == KH_NULL ? 0 : 1));
+                cq[QTAG * kQCap + j] = (double)((((int64_t)ray * 8 + ncross) << 1) | (kind == KH_NULL ? 0 : 1));
               }
               ++ncross;
             }
@@ -427,7 +423,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
         // written so that a NaN step size also ends the ray
         if (!(h >= 1e-12 * P.h_coeff * hscale(kind, (double)r_cur))) status = KH_FAILED;
       }
-      if (status == KH_ACTIVE && ++tries > 4 * P.max_steps + 1000) status = KH_MAX_STEPS;
+      if (status == KH_ACTIVE && ++tries > P.max_tries) status = KH_MAX_STEPS;
     }
 
     if (status != KH_ACTIVE) {
@@ -439,8 +435,9 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
       }
       S.h[ray] = h;
       S.lam[ray] = lam;
-      // the finalize pass adds atan2(y, x) to the winding part and clears the flags
-      S.phi[ray] = (P.k_cross > 0) ? (2.0 * M_PI) * wind : phi_in;
+      // the finalize pass adds atan2(y, x) to the winding part and clears the
+      // flags; without crossings the azimuth is not tracked and phi is left as is
+      if (P.k_cross > 0) S.phi[ray] = (2.0 * M_PI) * wind;
       S.status[ray] = status | kRetired | (P.k_cross > 0 ? kPhiPending : 0);
       S.n_acc[ray] = nacc;
       S.n_rej[ray] = nrej;
@@ -1006,7 +1003,7 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
     return fail(ctx, KH_EUNSUPPORTED, "the paper-form right-hand side is built for P64 and P32 only");
   const int block = p->block_size ? p->block_size : 256;
   if (block < 64 || block > 256 || block % 64) return fail(ctx, KH_EINVAL, "block_size must be 64, 128, 192 or 256");
-  const int refill = p->refill_min ? p->refill_min : 16;
+  const int refill = p->refill_min ? p->refill_min : 8;
   if (refill < 1 || refill > 64) return fail(ctx, KH_EINVAL, "refill_min must be in [1, 64]");
   if (p->grid_blocks < 0) return fail(ctx, KH_EINVAL, "grid_blocks must be >= 0");
   if (p->waves_per_eu < 0 || p->waves_per_eu > 8) return fail(ctx, KH_EINVAL, "waves_per_eu must be in [0, 8]");
@@ -1029,7 +1026,9 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   kp.r_escape = p->r_escape;
   kp.t_end = p->t_end;
   kp.r_fp64 = p->r_fp64;
-  kp.max_steps = p->max_steps;
+  // per-call step counters are 32-bit in the kernel
+  kp.max_steps = (int32_t)std::min<int64_t>(p->max_steps, INT32_MAX);
+  kp.max_tries = (int32_t)std::min<int64_t>(4 * std::min<int64_t>(p->max_steps, INT32_MAX) + 1000, INT32_MAX);
   kp.k_cross = p->k_cross;
   kp.refill_min = refill;
   kp.parts = p->queue_parts ? p->queue_parts : kParts;

@@ -90,6 +90,23 @@ __host__ __device__ inline float krcp_est(float x) { return krcp(x); }
 __host__ __device__ inline double ksqrt(double x) { return x * krsqrt(x > 1e-300 ? x : 1e-300); }
 __host__ __device__ inline float ksqrt(float x) { return x * krsqrt(x > 1e-30f ? x : 1e-30f); }
 
+// Azimuth estimate with |error| < 0.08 rad, enough to recover a winding count
+// by rounding: atan(|y|/|x|) = pi/4 + atan(u), u = (|y| - |x|) / (|y| + |x|),
+// with atan(u) ~ pi u / 4 on [-1, 1]; quadrants (and the sign of a zero)
+// follow atan2.
+__host__ __device__ inline double atan2_est(double y, double x) {
+  const float ax = fabsf((float)x), ay = fabsf((float)y);
+  const float s = ax + ay;
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float u = s > 0.0f ? (ay - ax) * __builtin_amdgcn_rcpf(s) : 0.0f;
+#else
+  const float u = s > 0.0f ? (ay - ax) / s : 0.0f;
+#endif
+  float t = 0.78539816f * (1.0f + u);
+  if (__builtin_signbit(x)) t = 3.14159265f - t;
+  return __builtin_signbit(y) ? -(double)t : (double)t;
+}
+
 template <typename T>
 struct Accel {
   T a[4];  // d k^mu / d lambda

@@ -57,4 +57,6 @@ double host_hermite_zero(double y0, double m0, double y1, double m1, double h) {
 void host_constants(double a, const double* x, const double* k, double* out) { kh::constants(a, x, k, out); }
 
 double host_redshift(double r, double xi, double a) { return kh::redshift(r, xi, a); }
+
+double host_atan2_est(double y, double x) { return kh::atan2_est(y, x); }
 }

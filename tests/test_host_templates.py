@@ -37,6 +37,8 @@ def H():
     L.host_constants.argtypes = [C.c_double, pd, pd, pd]
     L.host_redshift.argtypes = [C.c_double] * 3
     L.host_redshift.restype = C.c_double
+    L.host_atan2_est.argtypes = [C.c_double] * 2
+    L.host_atan2_est.restype = C.c_double
     return L
 
 
@@ -144,3 +146,24 @@ def test_hermite_zero_is_the_cubic_root(H):
         t2, t3 = th * th, th ** 3
         p = (2 * t3 - 3 * t2 + 1) * y0 + (t3 - 2 * t2 + th) * h * m0 + (-2 * t3 + 3 * t2) * y1 + (t3 - t2) * h * m1
         assert abs(p) < 1e-12 * (abs(y0) + abs(y1) + h * (abs(m0) + abs(m1)))
+
+
+def test_azimuth_estimate_recovers_winding(H):
+    """The integrator rebuilds the winding count w of a stored unwrapped azimuth
+    phi = atan2(y, x) + 2 pi w by rounding (phi - est) / 2 pi, so the estimate
+    must stay within pi of atan2 everywhere, including on the axes and for
+    signed zeros (where atan2 is +-pi or +-0)."""
+    pts = [(y, x) for y in (0.0, -0.0, 1.0, -1.0, 1e-300, -1e-300) for x in (0.0, -0.0, 2.0, -2.0, 1e-300, -1e-300)]
+    ang = rng.uniform(-np.pi, np.pi, 20000)
+    rad = 10 ** rng.uniform(-8, 8, ang.size)
+    pts += list(zip(rad * np.sin(ang), rad * np.cos(ang)))
+    worst = 0.0
+    for i, (y, x) in enumerate(pts):
+        true = np.arctan2(y, x)
+        est = H.host_atan2_est(y, x)
+        if i >= 36:  # off the origin (the first 36 points include zeros and FP32 underflow)
+            worst = max(worst, abs(est - true))
+        for w in (-3, -1, 0, 2, 5):
+            phi = true + 2 * np.pi * w
+            assert int(np.rint((phi - est) / (2 * np.pi))) == w, (y, x, w)
+    assert worst < 0.08 + 1e-6  # away from the origin the estimate is within 0.08 rad
