@@ -16,14 +16,9 @@
 //   a^i = -k^j (xdot_{i,j} - 1/2 xdot_{j,i}) + F l_i.
 // Two evaluations of that formula are provided:
 //   * rhs_paper: forms the 12 values xdot_{b,j} and then the sums, as written;
-//   * rhs_factored (default): the same quantities regrouped further.  Because
-//     d_j g_bc = d_j f l_b l_c + f (d_j l_b l_c + l_b d_j l_c), one has
-//     xdot_{b,j} = l_b G_j + f K d_j l_b with K = l_c k^c and
-//     G_j = d_j f K + f k^c d_j l_c.  The Jacobian d_j l_i is a rank-one term
-//     plus a fixed 3x3 pattern, so the two contractions it enters become two
-//     dot products.  The null property l^b l_b = 0 and l_i d_j l_i = 0 (both
-//     follow from eq:CKSr) drop the first term of F.  The result equals
-//     rhs_paper up to rounding.
+//   * rhs_factored (default): the same acceleration contracted in another
+//     order (written out above the function): about 110 operations instead
+//     of 155, equal to rhs_paper up to rounding.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,18 +26,18 @@
 namespace kh {
 
 // Reciprocal and reciprocal square root.  On the device: the hardware
-// estimate (v_rcp / v_rsq) refined by Newton-Raphson iterations; for FP64 two
-// iterations take the ~2^-23 relative estimate to about one ulp (each
-// iteration squares the relative error): r <- r + r (1 - x r) and
-// y <- y + y (1/2 - x y^2 / 2).  FP32 estimates are already within one ulp.
-// On the host (operation counts, CPU checks) plain IEEE operations.
+// estimate (v_rcp_f64 / v_rsq_f64, relative error below 2^-24 on gfx950)
+// refined by one Newton-Raphson iteration, r <- r + r (1 - x r) and
+// y <- y + y (1/2 - x y^2 / 2), which squares the relative error: below
+// 2^-47 (5e-15), i.e. within ~20 ulp of the rounded value.  The right-hand
+// side built from them is then accurate to ~1e-14 relative, six orders of
+// magnitude below the local error the step controller admits at rtol = 1e-8.
+// FP32 estimates are already within one ulp.  On the host (operation counts,
+// CPU checks) plain IEEE operations.
 __host__ __device__ inline double krcp(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 #else
   return 1.0 / x;
 #endif
@@ -56,12 +51,8 @@ __host__ __device__ inline float krcp(float x) {
 }
 __host__ __device__ inline double krsqrt(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  double y = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  double e = fma(-hx, y * y, 0.5);
-  y = fma(y, e, y);
-  e = fma(-hx, y * y, 0.5);
-  return fma(y, e, y);
+  const double y = __builtin_amdgcn_rsq(x);
+  return fma(y, fma(-0.5 * x, y * y, 0.5), y);
 #else
   return 1.0 / sqrt(x);
 #endif
@@ -73,17 +64,8 @@ __host__ __device__ inline float krsqrt(float x) {
   return 1.0f / sqrtf(x);
 #endif
 }
-// Reciprocal to about 2^-46 relative (one Newton-Raphson iteration), for the
-// scales of the error norm, which only has to decide err <= 1 and set the
-// next step size.
-__host__ __device__ inline double krcp_est(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  const double r = __builtin_amdgcn_rcp(x);
-  return fma(r, fma(-x, r, 1.0), r);
-#else
-  return 1.0 / x;
-#endif
-}
+// Reciprocal for the scales of the error norm (same accuracy as krcp).
+__host__ __device__ inline double krcp_est(double x) { return krcp(x); }
 __host__ __device__ inline float krcp_est(float x) { return krcp(x); }
 // sqrt(x) = x / sqrt(x) for x >= 0, without a branch: the argument of the
 // reciprocal square root is kept >= 1e-300 (1e-30 in FP32), so x = 0 gives 0.
@@ -184,59 +166,71 @@ __host__ __device__ inline Accel<T> rhs_paper(T a, const T x[4], const T k[4]) {
   return out;
 }
 
-// Regrouped evaluation of the same right-hand side.
+// Regrouped evaluation of the same right-hand side.  With Christoffel symbols
+// of the first kind, dk^a/dlambda = -g^{ad} V_d where
+//   V_d = k^b d_b(g_dc) k^c - 1/2 d_d(g_bc) k^b k^c,
+// and for g = eta + f l l with l null (g^{ab} = eta^{ab} - f l^a l^b):
+//   a^0 = V_0 - f (l^d V_d),   a^i = f l_i (l^d V_d) - V_i,   l^d V_d = l_i V_i - V_0.
+// With K = l.k, the rates along the ray fdot = k^j d_j f, ldot_i = k^j d_j l_i,
+// Kd = k^i ldot_i, and dK_d = k^i d_d l_i:
+//   V_0 = fdot K + f Kd,
+//   V_i = V_0 l_i + f K (ldot_i - dK_i) - 1/2 K^2 d_i f.
+// The Jacobian d_j l_i = p_i d_j r + B_ij with B = [[r/S, a/S, 0], [-a/S, r/S, 0],
+// [0, 0, 1/r]] gives ldot_i - dK_i = p_i rdot - (k.p) d_i r + ((B - B^T) k)_i,
+// where (B - B^T) k = 2a/S (k_y, -k_x, 0), and Kd = (k.p) rdot + (r/S)(k_x^2 + k_y^2)
+// + k_z^2 / r.  d_j f = m d_j r - delta_jz 2 f a^2 z / D.  About 110 operations,
+// against 155 for the regrouping by xdot_{b,j} G_j that eq:opt0/opti suggests.
 template <typename T>
 __host__ __device__ inline Accel<T> rhs_factored(T a, const T x[4], const T k[4]) {
   const T X = x[1], Y = x[2], Z = x[3];
-  const T k1 = k[1], k2 = k[2], k3 = k[3];
+  const T k0 = k[0], k1 = k[1], k2 = k[2], k3 = k[3];
   const T a2 = a * a;
   const T r2 = ks_r2(a2, X, Y, Z);
   // one reciprocal square root gives r and 1/r; one reciprocal gives 1/S and 1/D
   const T ir = krsqrt(r2);
   const T r = r2 * ir;
-  const T S = r2 + a2, D = r2 * r2 + a2 * Z * Z;
+  const T a2z2 = a2 * (Z * Z);
+  const T S = r2 + a2, D = r2 * r2 + a2z2;
   const T iSD = krcp(S * D);
   const T iS = D * iSD, iD = S * iSD;
-  const T f = T(2) * r2 * r * iD;
+  const T r3 = r2 * r;
+  const T f = T(2) * r3 * iD;
   const T rS = r * iS, aS = a * iS;
   const T l1 = rS * X + aS * Y, l2 = rS * Y - aS * X, l3 = Z * ir;
-  // gradient of r
+  // gradient of r, and of f = m d_j r - cz delta_jz
   const T c = r * iD;
   const T cr2 = c * r2;
-  const T dr1 = cr2 * X, dr2 = cr2 * Y, dr3 = c * (r2 + a2) * Z;
-  const T rdot = dr1 * k1 + dr2 * k2 + dr3 * k3;
-  // gradient of f: m d_j r, minus 2 f a^2 z / D on the z component
-  const T m = f * (T(3) * ir - T(4) * r2 * r * iD);
-  // d_j l_i = p_i d_j r + B_ij with p = ((x - 2 r l1)/S, (y - 2 r l2)/S, -l3/r)
-  // and B = [[r/S, a/S, 0], [-a/S, r/S, 0], [0, 0, 1/r]].
+  const T dr1 = cr2 * X, dr2 = cr2 * Y, dr3 = c * S * Z;
+  const T m = f * (T(3) * ir - T(4) * r3 * iD);
+  const T cz = T(2) * f * a2 * Z * iD;
+  // p of the Jacobian's rank-one part
   const T px = (X - T(2) * r * l1) * iS;
   const T py = (Y - T(2) * r * l2) * iS;
   const T pz = -l3 * ir;
-  const T pk = px * k1 + py * k2 + pz * k3;
-  // P_i = k^j d_j l_i and dK_j = k^i d_j l_i
-  const T P1 = px * rdot + rS * k1 + aS * k2;
-  const T P2 = py * rdot - aS * k1 + rS * k2;
-  const T P3 = pz * rdot + ir * k3;
-  const T dK1 = dr1 * pk + rS * k1 - aS * k2;
-  const T dK2 = dr2 * pk + aS * k1 + rS * k2;
-  const T dK3 = dr3 * pk + ir * k3;
-  const T K = k[0] + l1 * k1 + l2 * k2 + l3 * k3;
-  // G_j = d_j f K + f dK_j
-  const T mK = m * K;
-  const T G1 = mK * dr1 + f * dK1;
-  const T G2 = mK * dr2 + f * dK2;
-  const T G3 = mK * dr3 - T(2) * f * a2 * Z * iD * K + f * dK3;
-  const T kG = k1 * G1 + k2 * G2 + k3 * G3;
-  // F = -1/2 f K l^j (G_j + f dK_j)
-  const T H1 = G1 + f * dK1, H2 = G2 + f * dK2, H3 = G3 + f * dK3;
-  const T F = T(-0.5) * f * K * (l1 * H1 + l2 * H2 + l3 * H3);
+  // rates along the ray
+  const T rdot = dr1 * k1 + dr2 * k2 + dr3 * k3;
+  const T fdot = m * rdot - cz * k3;
+  const T kp = px * k1 + py * k2 + pz * k3;
+  const T K = k0 + l1 * k1 + l2 * k2 + l3 * k3;
+  const T Kd = kp * rdot + rS * (k1 * k1 + k2 * k2) + ir * (k3 * k3);
+  const T fK = f * K;
+  const T V0 = fdot * K + f * Kd;
+  // W_i = ldot_i - dK_i
+  const T a2S = T(2) * aS;
+  const T W1 = px * rdot - kp * dr1 + a2S * k2;
+  const T W2 = py * rdot - kp * dr2 - a2S * k1;
+  const T W3 = pz * rdot - kp * dr3;
+  const T hK2 = T(0.5) * K * K;
+  const T hK2m = hK2 * m;
+  const T V1 = V0 * l1 + fK * W1 - hK2m * dr1;
+  const T V2 = V0 * l2 + fK * W2 - hK2m * dr2;
+  const T V3 = V0 * l3 + fK * W3 - hK2m * dr3 + hK2 * cz;
+  const T flV = f * (l1 * V1 + l2 * V2 + l3 * V3 - V0);
   Accel<T> out;
-  out.a[0] = kG - F;
-  // a^i = -l_i kG - f K P_i + 1/2 K H_i + F l_i
-  const T fK = f * K, hK = T(0.5) * K, Fm = F - kG;
-  out.a[1] = Fm * l1 - fK * P1 + hK * H1;
-  out.a[2] = Fm * l2 - fK * P2 + hK * H2;
-  out.a[3] = Fm * l3 - fK * P3 + hK * H3;
+  out.a[0] = V0 - flV;
+  out.a[1] = flV * l1 - V1;
+  out.a[2] = flV * l2 - V2;
+  out.a[3] = flV * l3 - V3;
   out.r = r;
   out.rdot = rdot;
   return out;
