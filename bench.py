@@ -41,10 +41,14 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-# HBM bytes per launch of the FP64 DOPRI5 kernel from the committed rocprofv3
-# FETCH_SIZE / WRITE_SIZE runs (profiles/k_integrate_dopri5_fp64_kerr1024.md),
-# valid only for the kernel source they were taken on.
-PROFILED_TRAFFIC = {"source_hash": "fe2015b72478b1ad", "bytes": (119722.1875 * 2.0 + 309763.1875 * 1.0) * 1024}
+# From the committed rocprofv3 runs of the FP64 DOPRI5 kernel on this workload
+# (profiles/k_integrate_dopri5_fp64_kerr1024.md): HBM bytes per launch
+# (FETCH_SIZE, WRITE_SIZE, calibrated against a plain copy) and hardware FP64
+# FLOP per launch (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes), valid only for the
+# kernel source they were taken on.
+PROFILED = {"source_hash": "2d70ae41a0c952d0",
+            "traffic_bytes": (121587.125 * 2.0 + 323664.375 * 1.0) * 1024,
+            "hw_fp64_flops": 6203319763.0 * 64}
 
 
 def algorithmic_flops(K, stats, n_rays, method, form):
@@ -105,6 +109,8 @@ def run_gpu(args):
     ms_step = 1e3 * wall / args.steps
     kern_s = np.mean(kern_ms) / 1e3
     tflops = flops / kern_s / 1e12
+    profiled = kernel_source_hash() == PROFILED["source_hash"]
+    hw_tflops = PROFILED["hw_fp64_flops"] / kern_s / 1e12 if profiled else None
     out = dict(
         metric="rays/s and RHS evals/s at a=0.99 1024^2; surrogate vs integrator at fixed error",
         value=n * args.steps / wall,
@@ -128,10 +134,12 @@ def run_gpu(args):
         integrate_kernel_ms=float(np.mean(kern_ms)),
         roofline=dict(bound="alu", achieved=tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                       frac=tflops / FP64_PEAK_TFLOPS,
-                      traffic=(PROFILED_TRAFFIC["bytes"] if kernel_source_hash() == PROFILED_TRAFFIC["source_hash"]
-                               else None),
+                      traffic=PROFILED["traffic_bytes"] if profiled else None,
                       traffic_unit="bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
-                      flops_per_launch=flops, flop_per_rhs=rhs_f, flop_per_attempt_overhead=step_f),
+                      flops_per_launch=flops, flop_per_rhs=rhs_f, flop_per_attempt_overhead=step_f,
+                      hw_achieved=hw_tflops, hw_frac=(hw_tflops / FP64_PEAK_TFLOPS if hw_tflops else None),
+                      hw_note="hardware-counted FP64 FLOP (FMA = 2, all lanes of issued instructions) of the "
+                              "profiled build / this run's kernel time"),
     )
     if not args.no_extras:
         out["extras"] = extras(args, ctx, K, W, torch)

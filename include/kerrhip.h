@@ -97,6 +97,11 @@ typedef struct {
   int32_t k_cross;  /* 0..8 crossing slots per geodesic */
   double *c0;       /* [4][n] = (E, L_z, Q, mu^2) at initialisation, or NULL */
   double *c1;       /* [4][n] = the same at the end of the last integrate call, or NULL */
+  int32_t *order;   /* [ceil(n / 64)] or NULL: tiles of 64 consecutive ray ids (tile t = ids 64t .. 64t + 63)
+                       in the order kh_integrate hands them out; NULL = natural order.  kh_init_rays writes
+                       it longest-expected-first (see there), the other init calls write the natural order.
+                       A caller-written order must be a permutation of the tile numbers; entries out of range
+                       are skipped by the integrator (their rays are then not integrated). */
 } kh_state;
 
 /* Integration rules.  Defaults (kh_default_params): DOPRI5, FP64,
@@ -117,7 +122,7 @@ typedef struct {
   int64_t max_steps; /* accepted steps per call before KH_MAX_STEPS (> 0) */
   int32_t block_size;   /* threads per block: 64, 128, 192 or 256; 0 = 256 */
   int32_t grid_blocks;  /* persistent grid size; 0 = fill the device from the occupancy query */
-  int32_t refill_min;   /* a wave refills once at least this many lanes are idle (1..64); 0 = 8 */
+  int32_t refill_min;   /* a wave refills once at least this many lanes are idle (1..64); 0 = 16 */
   int32_t waves_per_eu; /* register budget of the kernel variant: 0 or 1 = compiler's choice; DOPRI5 with
                            the factored form also has 3 and 4 (FP64 / mixed) and 4 and 5 (FP32) */
   int32_t queue_parts;  /* work-queue partitions of the ray range (1..8); 0 = 8, one per XCD: chunks of 8192
@@ -150,14 +155,25 @@ void kh_default_params(kh_params *p);
 
 /* Initial states of the rays of n_cams images (host array `cams`), concatenated
  * in camera order: the rays of camera c occupy ids [off_c, off_c + w_c h_c).
+ * If st->order is set, the call also orders the 64-ray tiles for integration,
+ * longest first: a ray near the critical curve circles the hole many times
+ * and takes several times the median number of steps, so it has to start
+ * early or the launch waits for it at the end.  Each ray's priority is how
+ * close its radial potential R(r) = (r^2 + a^2 - a xi)^2 - Delta (eta + (xi - a)^2)
+ * (xi = L_z / E, eta = Q / E^2) comes to a double root between the horizon and
+ * r = 5, on a log scale; a tile takes the maximum over its rays and the tiles
+ * are counting-sorted on that key (the order within a key is unspecified).  The
+ * results of kh_integrate do not depend on the order, only its run time.
  * Requires st->n == sum of width*height.  Writes s, spin, kind (KH_NULL),
  * h = 0, lam = 0, phi = atan2(y, x), status, n_acc = n_rej = 0, n_cross = 0,
  * cross = NaN and c0.  The camera table is copied to the context (one small
  * host-to-device copy on `stream`).  cams == NULL reuses the table of the last
  * call on this context (same n_cams): then the call is one kernel launch and
- * may be captured into a HIP graph; a captured launch reads the context's table
- * when the graph is replayed, so upload no other table on that context while
- * the graph is in use. */
+ * may be captured into a HIP graph (then two launches with st->order set; the
+ * context's tile-key buffer must already be large enough, i.e. an earlier call
+ * outside capture had at least as many rays); a captured launch reads the
+ * context's table when the graph is replayed, so upload no other table on
+ * that context while the graph is in use. */
 kh_status kh_init_rays(kh_ctx *ctx, const kh_camera *cams, int32_t n_cams, kh_state *st, void *stream);
 
 /* Rays with individual parameters (device arrays [n]): physical spin, inclination,

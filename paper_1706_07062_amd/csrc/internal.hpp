@@ -22,6 +22,8 @@ struct kh_ctx {
   kh_camera* h_cams = nullptr;  // pinned staging
   int64_t* h_offs = nullptr;
   hipEvent_t cam_evt = nullptr;
+  uint8_t* d_keys = nullptr;  // per-tile scheduling keys of kh_init_rays
+  int64_t keys_cap = 0;
   std::string err;
 };
 
@@ -43,6 +45,7 @@ struct KState {
   int32_t k_cross;
   double* c0;
   double* c1;
+  int32_t* order;  // tile permutation or nullptr
 };
 
 struct KParams {
@@ -71,6 +74,7 @@ inline KState to_k(const kh_state* st) {
   k.k_cross = st->k_cross;
   k.c0 = st->c0;
   k.c1 = st->c1;
+  k.order = st->order;
   return k;
 }
 

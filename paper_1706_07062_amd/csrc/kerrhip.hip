@@ -30,7 +30,7 @@ using namespace khi;
 // The Python binding mirrors these layouts with ctypes.
 static_assert(sizeof(kh_camera) == 64, "kh_camera layout");
 static_assert(sizeof(kh_params) == 112, "kh_params layout");
-static_assert(sizeof(kh_state) == 120, "kh_state layout");
+static_assert(sizeof(kh_state) == 128, "kh_state layout");
 
 namespace {
 
@@ -141,6 +141,18 @@ __device__ inline int64_t wave_grab(unsigned long long idle, unsigned long long*
   return -1;
 }
 
+// Queue position -> ray id: through the tile order when there is one.  Every
+// index is checked, so a malformed order can skip rays but never read or write
+// outside the state.
+__device__ inline int64_t queue_id(int64_t pos, const KState& S, int64_t n_tiles) {
+  if (pos < 0 || !S.order) return pos;
+  const int64_t t = pos >> 6;
+  if (t >= n_tiles) return -1;
+  const int64_t tile = S.order[t];
+  const int64_t id = tile * 64 + (pos & 63);
+  return (tile >= 0 && tile < n_tiles && id < S.n) ? id : -1;
+}
+
 // ---------------------------------------------------------------------------
 // Equatorial crossings: a lane that sees a sign change of z only queues the
 // two nodes of the step in its wave's LDS queue; the wave refines queued
@@ -216,6 +228,9 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
   }
   const int parts = P.parts;
   const int home = blockIdx.x % parts;
+  // with a tile order the queue runs over whole tiles (ids past n are skipped)
+  const int64_t n_tiles = (n + 63) >> 6;
+  const int64_t nq = S.order ? n_tiles * 64 : n;
   int cursor = 0;  // partitions this wave has seen drained (wave-uniform)
   bool fresh = false;
 
@@ -241,7 +256,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
     // ---- refill idle lanes (wave-uniform decision) ----
     const unsigned long long idle = __ballot(ray < 0);
     if (cursor < parts && idle != 0ull && (__popcll(idle) >= P.refill_min || idle == ~0ull)) {
-      const int64_t id = wave_grab(idle, qctr, n, home, parts, cursor);
+      const int64_t id = queue_id(wave_grab(idle, qctr, nq, home, parts, cursor), S, n_tiles);
       if (ray < 0 && id >= 0) {
         const int st = S.status[id];
         if (st == KH_ACTIVE || st == KH_MAX_STEPS) {
@@ -521,26 +536,108 @@ __device__ inline void camera_ray(double a_phys, double d, double incl, double a
   *ok = *ok && (y[4] == y[4]);
 }
 
-__global__ void k_init_rays(const kh_camera* cams, const int64_t* offs, int n_cams, KState S) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= S.n) return;
-  int lo = 0, hi = n_cams - 1;  // last camera with offs[c] <= i
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (offs[mid] <= i)
-      lo = mid;
-    else
-      hi = mid - 1;
+// Scheduling priority of a null ray (0 .. 255, larger = expected to take more
+// steps): with xi = L_z / E and eta = Q / E^2 in the chart of spin a, the radial
+// potential R(r) = (r^2 + a^2 - a xi)^2 - Delta (eta + (xi - a)^2) has a double
+// root on a spherical photon orbit; the closer its minimum between the horizon
+// and r = 5 comes to zero, the more times the ray circles the hole.  The
+// minimum is bracketed on 17 radii and refined by three Newton steps on R'.
+__device__ inline int ray_priority(double a, const double y[8]) {
+  double cst[4];
+  constants(a, y, y + 4, cst);
+  const double E = cst[0];
+  if (!(E > 0.0) || !(cst[1] == cst[1]) || !(cst[2] == cst[2])) return 0;
+  const double xi = cst[1] / E, eta = cst[2] / (E * E);
+  const double a2 = a * a, B = a2 - a * xi, Cc = eta + (xi - a) * (xi - a);
+  const double rh = 1.0 + ksqrt(1.0 - a2 > 0.0 ? 1.0 - a2 : 0.0), span = 5.0 - rh;
+  double rb = rh, Rb = 1e300;
+  for (int j = 0; j <= 16; ++j) {
+    const double r = rh + span * (j * (1.0 / 16));
+    const double P = r * r + B;
+    const double v = P * P - (r * r - 2.0 * r + a2) * Cc;
+    if (v < Rb) {
+      Rb = v;
+      rb = r;
+    }
   }
-  const kh_camera cam = cams[lo];
-  const int64_t p = i - offs[lo];
-  const int64_t row = p / cam.width, col = p % cam.width;
-  const double al = cam.alpha_min + (col + 0.5) * (cam.alpha_max - cam.alpha_min) / cam.width;
-  const double be = cam.beta_min + (row + 0.5) * (cam.beta_max - cam.beta_min) / cam.height;
-  double y[8];
-  bool ok;
-  camera_ray(cam.a, cam.r_obs, cam.incl, al, be, y, &ok);
-  finish_init(S, i, y, cam.a, KH_NULL, ok);
+  for (int it = 0; it < 3; ++it) {
+    const double P = rb * rb + B;
+    const double d1 = 4.0 * rb * P - (2.0 * rb - 2.0) * Cc;
+    const double d2 = 4.0 * P + 8.0 * rb * rb - 2.0 * Cc;
+    if (d2 > 0.0) {
+      const double rn = rb - d1 / d2;
+      rb = rn < rh ? rh : (rn > 5.0 ? 5.0 : rn);
+    }
+  }
+  const double P = rb * rb + B;
+  const double v = P * P - (rb * rb - 2.0 * rb + a2) * Cc;
+  Rb = v < Rb ? v : Rb;
+  const double pr = -log2(fabs(Rb) * (1.0 / 30.0) + 1e-12);  // ~ -20 .. 40
+  const int key = (int)(4.0 * pr) + 64;
+  return key < 0 ? 0 : (key > 255 ? 255 : key);
+}
+
+// keys (optional): per-tile scheduling key, the maximum of ray_priority over
+// the tile's 64 rays (one wave = one tile: blocks are multiples of 64 threads).
+__global__ void k_init_rays(const kh_camera* cams, const int64_t* offs, int n_cams, KState S, uint8_t* keys) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int key = 0;
+  if (i < S.n) {
+    int lo = 0, hi = n_cams - 1;  // last camera with offs[c] <= i
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (offs[mid] <= i)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const kh_camera cam = cams[lo];
+    const int64_t p = i - offs[lo];
+    const int64_t row = p / cam.width, col = p % cam.width;
+    const double al = cam.alpha_min + (col + 0.5) * (cam.alpha_max - cam.alpha_min) / cam.width;
+    const double be = cam.beta_min + (row + 0.5) * (cam.beta_max - cam.beta_min) / cam.height;
+    double y[8];
+    bool ok;
+    camera_ray(cam.a, cam.r_obs, cam.incl, al, be, y, &ok);
+    finish_init(S, i, y, cam.a, KH_NULL, ok);
+    if (keys && ok) key = ray_priority(-cam.a, y);
+  }
+  if (keys) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int other = __shfl_xor(key, o);
+      key = other > key ? other : key;
+    }
+    if (__lane_id() == 0 && (i >> 6) < ((S.n + 63) >> 6)) keys[i >> 6] = (uint8_t)key;
+  }
+}
+
+// Counting sort of the tiles on their keys, largest key first, in one block.
+constexpr int kSortThreads = 1024;
+__global__ void __launch_bounds__(kSortThreads) k_tile_order(const uint8_t* keys, int64_t n_tiles, int32_t* order) {
+  __shared__ unsigned hist[256];
+  __shared__ unsigned next[256];
+  for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0u;
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < n_tiles; t += blockDim.x) atomicAdd(&hist[keys[t]], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned acc = 0;
+    for (int b = 255; b >= 0; --b) {
+      next[b] = acc;
+      acc += hist[b];
+    }
+  }
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+    const unsigned pos = atomicAdd(&next[keys[t]], 1u);
+    order[pos] = (int32_t)t;
+  }
+}
+
+__global__ void k_order_identity(int32_t* order, int64_t n_tiles) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_tiles) order[t] = (int32_t)t;
 }
 
 __global__ void k_init_rays_pixels(kh_camera cam, const int32_t* pix, KState S) {
@@ -742,6 +839,8 @@ kh_status check_state(kh_ctx* ctx, const kh_state* st, bool need_cross) {
       return fail(ctx, KH_EINVAL, "state arrays c0, c1, cross must be NULL or 8-byte aligned device memory");
   if (st->n_cross && (!aligned(st->n_cross, 4) || !device_ok(st->n_cross)))
     return fail(ctx, KH_EINVAL, "state.n_cross must be NULL or 4-byte aligned device memory");
+  if (st->order && (!aligned(st->order, 4) || !device_ok(st->order)))
+    return fail(ctx, KH_EINVAL, "state.order must be NULL or 4-byte aligned device memory");
   if (need_cross && st->k_cross > 0 && (!st->cross || !st->n_cross))
     return fail(ctx, KH_EINVAL, "state.k_cross > 0 requires cross and n_cross");
   return KH_OK;
@@ -841,11 +940,52 @@ kh_status kh_destroy(kh_ctx* c) {
   if (c->h_cams) (void)hipHostFree(c->h_cams);
   if (c->h_offs) (void)hipHostFree(c->h_offs);
   if (c->cam_evt) (void)hipEventDestroy(c->cam_evt);
+  if (c->d_keys) (void)hipFree(c->d_keys);
   delete c;
   return KH_OK;
 }
 
 const char* kh_last_error(const kh_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+namespace {
+// The init kernel over the uploaded camera table, then (with st->order) the
+// tile sort.  The key buffer grows only outside graph capture.
+kh_status launch_init_rays(kh_ctx* ctx, kh_state* st, int n_cams, hipStream_t strm) {
+  const int64_t n_tiles = (st->n + 63) / 64;
+  uint8_t* keys = nullptr;
+  if (st->order) {
+    if (n_tiles > ctx->keys_cap) {
+      if (g_skip_ptr_query)
+        return fail(ctx, KH_EINVAL, "the tile-key buffer must grow: call kh_init_rays once outside graph capture");
+      if (ctx->d_keys) KH_HIP(ctx, hipFree(ctx->d_keys));
+      ctx->d_keys = nullptr;
+      ctx->keys_cap = 0;
+      if (hipMalloc(&ctx->d_keys, (size_t)n_tiles) != hipSuccess) return fail(ctx, KH_ENOMEM, "tile-key buffer");
+      ctx->keys_cap = n_tiles;
+    }
+    keys = ctx->d_keys;
+  }
+  const KState ks = to_k(st);
+  const int block = 256;
+  const int64_t grid = (st->n + block - 1) / block;
+  hipLaunchKernelGGL(k_init_rays, dim3((unsigned)grid), dim3(block), 0, strm, ctx->d_cams, ctx->d_offs, n_cams, ks,
+                     keys);
+  KH_HIP(ctx, hipGetLastError());
+  if (st->order) {
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kSortThreads), 0, strm, (const uint8_t*)keys, n_tiles, st->order);
+    KH_HIP(ctx, hipGetLastError());
+  }
+  return KH_OK;
+}
+
+kh_status natural_order(kh_ctx* ctx, const kh_state* st, hipStream_t strm) {
+  if (!st->order) return KH_OK;
+  const int64_t n_tiles = (st->n + 63) / 64;
+  hipLaunchKernelGGL(k_order_identity, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, strm, st->order, n_tiles);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+}  // namespace
 
 kh_status kh_init_rays(kh_ctx* ctx, const kh_camera* cams, int32_t n_cams, kh_state* st, void* stream) {
   if (!ctx) return KH_EINVAL;
@@ -859,13 +999,7 @@ kh_status kh_init_rays(kh_ctx* ctx, const kh_camera* cams, int32_t n_cams, kh_st
     if (s != KH_OK) return s;
     if (st->n != ctx->cams_total) return fail(ctx, KH_EINVAL, "state.n must equal the total pixel count of the cameras");
     if ((s = set_device(ctx)) != KH_OK) return s;
-    const KState ks = to_k(st);
-    const int block = 256;
-    const int64_t grid = (st->n + block - 1) / block;
-    hipLaunchKernelGGL(k_init_rays, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)stream, ctx->d_cams,
-                       ctx->d_offs, n_cams, ks);
-    KH_HIP(ctx, hipGetLastError());
-    return KH_OK;
+    return launch_init_rays(ctx, st, n_cams, (hipStream_t)stream);
   }
   int64_t total = 0;
   for (int i = 0; i < n_cams; ++i) {
@@ -915,12 +1049,7 @@ kh_status kh_init_rays(kh_ctx* ctx, const kh_camera* cams, int32_t n_cams, kh_st
   KH_HIP(ctx, hipEventRecord(ctx->cam_evt, strm));
   ctx->cams_uploaded = n_cams;
   ctx->cams_total = total;
-  const KState ks = to_k(st);
-  const int block = 256;
-  const int64_t grid = (st->n + block - 1) / block;
-  hipLaunchKernelGGL(k_init_rays, dim3((unsigned)grid), dim3(block), 0, strm, ctx->d_cams, ctx->d_offs, n_cams, ks);
-  KH_HIP(ctx, hipGetLastError());
-  return KH_OK;
+  return launch_init_rays(ctx, st, n_cams, strm);
 }
 
 kh_status kh_init_rays_list(kh_ctx* ctx, const double* spin, const double* incl, const double* alpha,
@@ -941,7 +1070,7 @@ kh_status kh_init_rays_list(kh_ctx* ctx, const double* spin, const double* incl,
   hipLaunchKernelGGL(k_init_rays_list, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)stream, spin, incl, alpha,
                      beta, r_obs, ks);
   KH_HIP(ctx, hipGetLastError());
-  return KH_OK;
+  return natural_order(ctx, st, (hipStream_t)stream);
 }
 
 kh_status kh_init_rays_pixels(kh_ctx* ctx, const kh_camera* cam, const int32_t* pix, kh_state* st, void* stream) {
@@ -958,7 +1087,7 @@ kh_status kh_init_rays_pixels(kh_ctx* ctx, const kh_camera* cam, const int32_t* 
   hipLaunchKernelGGL(k_init_rays_pixels, dim3((unsigned)((st->n + block - 1) / block)), dim3(block), 0,
                      (hipStream_t)stream, *cam, pix, ks);
   KH_HIP(ctx, hipGetLastError());
-  return KH_OK;
+  return natural_order(ctx, st, (hipStream_t)stream);
 }
 
 kh_status kh_init_geodesics(kh_ctx* ctx, int32_t kind, const double* spin, const double* x3, const double* v3,
@@ -979,7 +1108,7 @@ kh_status kh_init_geodesics(kh_ctx* ctx, int32_t kind, const double* spin, const
   hipLaunchKernelGGL(k_init_geodesics, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)stream, (int)kind, spin,
                      x3, v3, ks);
   KH_HIP(ctx, hipGetLastError());
-  return KH_OK;
+  return natural_order(ctx, st, (hipStream_t)stream);
 }
 
 kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stream) {
@@ -1003,7 +1132,7 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
     return fail(ctx, KH_EUNSUPPORTED, "the paper-form right-hand side is built for P64 and P32 only");
   const int block = p->block_size ? p->block_size : 256;
   if (block < 64 || block > 256 || block % 64) return fail(ctx, KH_EINVAL, "block_size must be 64, 128, 192 or 256");
-  const int refill = p->refill_min ? p->refill_min : 8;
+  const int refill = p->refill_min ? p->refill_min : 16;
   if (refill < 1 || refill > 64) return fail(ctx, KH_EINVAL, "refill_min must be in [1, 64]");
   if (p->grid_blocks < 0) return fail(ctx, KH_EINVAL, "grid_blocks must be >= 0");
   if (p->waves_per_eu < 0 || p->waves_per_eu > 8) return fail(ctx, KH_EINVAL, "waves_per_eu must be in [0, 8]");

@@ -322,3 +322,49 @@ def test_argument_errors(ctx):
     with pytest.raises(K.KerrHipError, match="device memory"):
         ctx.kh_integrate(K.kh_default_params(), st)
     st.c.h = saved
+
+
+def test_tile_order_is_a_permutation_and_does_not_change_results(ctx):
+    """kh_init_rays orders the 64-ray tiles longest-expected-first.  The order is
+    a permutation of the tiles (also with a ragged last tile), the tiles it puts
+    first really are the expensive ones, and integrating in that order gives
+    bitwise the results of the natural order."""
+    say("tile order")
+    cams = [W.Camera(0.99, 1000.0, 60.0, -12.0, 12.0, -12.0, 12.0, 97, 83),
+            W.Camera(0.5, 1000.0, 30.0, -9.0, 11.0, -10.0, 10.0, 61, 45)]
+    n = sum(c.n for c in cams)
+    assert n % 64 != 0
+    p = K.kh_default_params(k_cross=4)
+    ordered = gpu_image(ctx, cams, p, k_cross=4)
+    order = ordered.order.cpu().numpy()
+    n_tiles = (n + 63) // 64
+    assert np.array_equal(np.sort(order), np.arange(n_tiles))
+    st = K.State(n, k_cross=4, schedule=False)
+    ctx.kh_init_rays([kcam(c) for c in cams], st)
+    ctx.kh_integrate(p, st)
+    torch.cuda.synchronize()
+    a, b = ordered.numpy(), st.numpy()
+    for name in ("s", "status", "n_acc", "n_rej", "cross", "n_cross", "phi", "lam", "h"):
+        assert np.array_equal(a[name], b[name], equal_nan=True), name
+    # the first tenth of the order holds the costliest tiles
+    cost = (a["n_acc"] + a["n_rej"]).astype(np.float64)
+    tile_cost = np.array([cost[64 * t:64 * t + 64].max() for t in range(n_tiles)])
+    head = tile_cost[order[:max(1, n_tiles // 10)]]
+    say(f"  max steps: first tenth of the order {head.mean():.0f}, all tiles {tile_cost.mean():.0f}")
+    assert head.mean() > tile_cost.mean()
+    assert tile_cost.max() in head
+
+
+def test_out_of_range_tile_order_is_skipped(ctx):
+    """A caller-written order with entries out of range: the integrator skips
+    those positions (no access outside the state) and leaves the rays active."""
+    say("bad tile order")
+    cam = W.kerr_image(60.0, side=16)
+    st = K.State(cam.n)
+    ctx.kh_init_rays([kcam(cam)], st)
+    st.order.copy_(torch.tensor([1, 1000, -5, 2], dtype=torch.int32))  # tiles 0 and 3 never handed out
+    ctx.kh_integrate(K.kh_default_params(), st)
+    torch.cuda.synchronize()
+    g = st.numpy()
+    assert np.all(g["status"][0:64] == K.ACTIVE) and np.all(g["status"][192:256] == K.ACTIVE)
+    assert np.all(g["status"][64:192] != K.ACTIVE)
