@@ -245,6 +245,25 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
   int steps = 0, tries = 0;  // bounded by max_steps and max_tries (< 2^31)
   bool after_reject = false;
 
+  // ---- retire: write the ray back and free the lane ----
+  auto retire = [&]() {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      S.s[c * n + ray] = (double)x[c];
+      S.s[(4 + c) * n + ray] = (double)k[c];
+    }
+    S.h[ray] = h;
+    S.lam[ray] = lam;
+    // the finalize pass adds atan2(y, x) to the winding part and clears the
+    // flags; without crossings the azimuth is not tracked and phi is left as is
+    if (P.k_cross > 0) S.phi[ray] = (2.0 * M_PI) * wind;
+    S.status[ray] = status | kRetired | (P.k_cross > 0 ? kPhiPending : 0);
+    S.n_acc[ray] = nacc;
+    S.n_rej[ray] = nrej;
+    if (S.n_cross) S.n_cross[ray] = ncross;
+    ray = -1;
+  };
+
   while (true) {
     // ---- refine queued crossings with the whole wave (uniform point) ----
     if (P.k_cross > 0) {
@@ -289,9 +308,12 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
       if (cursor >= parts) break;
       continue;
     }
-    if (ray < 0) continue;
+    // RK4 lanes without a ray skip the rest of this pass.  DOPRI5 keeps the
+    // whole wave together: its attempt loop below decides when to leave by
+    // ballots that must see every lane, idle ones included.
+    if (METHOD == KH_RK4 && ray < 0) continue;
 
-    // ---- first-stage acceleration of a freshly loaded ray ----
+    // ---- first-stage acceleration of a freshly loaded ray (idle lanes have fresh = false) ----
     if (fresh || METHOD == KH_RK4) {
       const Accel<TS> ra = rhs<FORM, TS>(a_c, x, k);
 #pragma unroll
@@ -340,125 +362,127 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
         continue;
       }
     } else {
-      TS xn[4], kn[4], a7[4], r_new, rdot_new;
-      const TS hs = (TS)h;
-      const TS rtol = (TS)P.rtol, atol = (TS)P.atol;
-      TS err2;  // squared RMS error norm
-      if (PREC == KH_PMIXED && __ballot(r_cur < (TS)P.r_fp64) == 0ull)
-        err2 = dp5_attempt<FORM, TS, TF>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
-      else
-        err2 = dp5_attempt<FORM, TS, TS>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
+      // Attempts until the wave needs service (refill, crossing flush):
+      // one entry and one back-edge keep the ray state in fixed registers.
+      // Every lane runs this loop (idle lanes skip the attempt), so the exit
+      // ballots count all 64 lanes; each ray retires within max_tries
+      // attempts, hence all lanes become idle and the loop ends.
+      while (true) {
+        if (ray >= 0) {
+          TS xn[4], kn[4], a7[4], r_new, rdot_new;
+          const TS hs = (TS)h;
+          const TS rtol = (TS)P.rtol, atol = (TS)P.atol;
+          TS err2;  // squared RMS error norm
+          if (PREC == KH_PMIXED && __ballot(r_cur < (TS)P.r_fp64) == 0ull)
+            err2 = dp5_attempt<FORM, TS, TF>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
+          else
+            err2 = dp5_attempt<FORM, TS, TS>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
 
-      const TS raw = TS(0.9) * kpow_m1_10(err2);
-      if (err2 <= TS(1)) {
-        ++nacc;
-        ++steps;
-        bool bad = false;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) bad = bad || (xn[c] != xn[c]) || (kn[c] != kn[c]);
-        const double lam_old = lam;
-        lam += h;
-        if (bad) {
-          status = KH_FAILED;
-        } else {
-          if (P.k_cross > 0) {
-            // Unwrapped azimuth; equatorial crossings are queued for the wave.
-            const double x0 = x[1], y0 = x[2], z0 = x[3];
-            const double x1 = xn[1], y1 = xn[2], z1 = xn[3];
-            const int wind0 = wind;
-            const double crs = x0 * y1 - y0 * x1;
-            wind += (y0 >= 0.0 && y1 < 0.0 && crs > 0.0) - (y0 < 0.0 && y1 >= 0.0 && crs < 0.0);
-            if ((z0 < 0.0 && z1 > 0.0) || (z0 > 0.0 && z1 < 0.0) || (z1 == 0.0 && z0 != 0.0)) {
-              if (ncross < S.k_cross && ncross < P.k_cross) {
-                const int j = atomicAdd(cq_count, 1);  // < kQCap: flushed before 64 more can arrive
-                cq[QX0 * kQCap + j] = x0;
-                cq[QY0 * kQCap + j] = y0;
-                cq[QZ0 * kQCap + j] = z0;
-                cq[QKX0 * kQCap + j] = (double)k[1];
-                cq[QKY0 * kQCap + j] = (double)k[2];
-                cq[QKZ0 * kQCap + j] = (double)k[3];
-                cq[QX1 * kQCap + j] = x1;
-                cq[QY1 * kQCap + j] = y1;
-                cq[QZ1 * kQCap + j] = z1;
-                cq[QK01 * kQCap + j] = (double)kn[0];
-                cq[QKX1 * kQCap + j] = (double)kn[1];
-                cq[QKY1 * kQCap + j] = (double)kn[2];
-                cq[QKZ1 * kQCap + j] = (double)kn[3];
-                cq[QH * kQCap + j] = h;
-                cq[QAC * kQCap + j] = (double)a_c;
-                cq[QWIND * kQCap + j] = (double)wind0;
-                cq[QTAG * kQCap + j] = (double)((((int64_t)ray * 8 + ncross) << 1) | (kind == KH_NULL ? 0 : 1));
+          const TS raw = TS(0.9) * kpow_m1_10(err2);
+          if (err2 <= TS(1)) {
+            ++nacc;
+            ++steps;
+            bool bad = false;
+    #pragma unroll
+            for (int c = 0; c < 4; ++c) bad = bad || (xn[c] != xn[c]) || (kn[c] != kn[c]);
+            const double lam_old = lam;
+            lam += h;
+            if (bad) {
+              status = KH_FAILED;
+            } else {
+              if (P.k_cross > 0) {
+                // Unwrapped azimuth; equatorial crossings are queued for the wave.
+                const double x0 = x[1], y0 = x[2], z0 = x[3];
+                const double x1 = xn[1], y1 = xn[2], z1 = xn[3];
+                const int wind0 = wind;
+                const double crs = x0 * y1 - y0 * x1;
+                wind += (y0 >= 0.0 && y1 < 0.0 && crs > 0.0) - (y0 < 0.0 && y1 >= 0.0 && crs < 0.0);
+                if ((z0 < 0.0 && z1 > 0.0) || (z0 > 0.0 && z1 < 0.0) || (z1 == 0.0 && z0 != 0.0)) {
+                  if (ncross < S.k_cross && ncross < P.k_cross) {
+                    const int j = atomicAdd(cq_count, 1);  // < kQCap: flushed before 64 more can arrive
+                    cq[QX0 * kQCap + j] = x0;
+                    cq[QY0 * kQCap + j] = y0;
+                    cq[QZ0 * kQCap + j] = z0;
+                    cq[QKX0 * kQCap + j] = (double)k[1];
+                    cq[QKY0 * kQCap + j] = (double)k[2];
+                    cq[QKZ0 * kQCap + j] = (double)k[3];
+                    cq[QX1 * kQCap + j] = x1;
+                    cq[QY1 * kQCap + j] = y1;
+                    cq[QZ1 * kQCap + j] = z1;
+                    cq[QK01 * kQCap + j] = (double)kn[0];
+                    cq[QKX1 * kQCap + j] = (double)kn[1];
+                    cq[QKY1 * kQCap + j] = (double)kn[2];
+                    cq[QKZ1 * kQCap + j] = (double)kn[3];
+                    cq[QH * kQCap + j] = h;
+                    cq[QAC * kQCap + j] = (double)a_c;
+                    cq[QWIND * kQCap + j] = (double)wind0;
+                    cq[QTAG * kQCap + j] = (double)((((int64_t)ray * 8 + ncross) << 1) | (kind == KH_NULL ? 0 : 1));
+                  }
+                  ++ncross;
+                }
               }
-              ++ncross;
+              if ((double)r_new < rcap)
+                status = KH_CAPTURED;
+              else if ((double)r_new > P.r_escape && rdot_new > TS(0))
+                status = KH_ESCAPED;
+              else if (P.t_end > 0.0 && (double)xn[0] >= P.t_end) {
+                // Land on t = t_end with the cubic Hermite interpolant of t(lambda);
+                // positions use dx/dlambda = k, momenta use dk/dlambda = acc.
+                const double th = hermite_zero((double)x[0] - P.t_end, (double)k[0], (double)xn[0] - P.t_end,
+                                               (double)kn[0], h);
+                TS xl[4], kl[4];
+    #pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                  xl[c] = (TS)herm(th, (double)x[c], (double)k[c], (double)xn[c], (double)kn[c], h);
+                  kl[c] = (TS)herm(th, (double)k[c], (double)a1[c], (double)kn[c], (double)a7[c], h);
+                }
+    #pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                  xn[c] = xl[c];
+                  kn[c] = kl[c];
+                }
+                lam = lam_old + th * h;
+                status = KH_T_END;
+              }
             }
-          }
-          if ((double)r_new < rcap)
-            status = KH_CAPTURED;
-          else if ((double)r_new > P.r_escape && rdot_new > TS(0))
-            status = KH_ESCAPED;
-          else if (P.t_end > 0.0 && (double)xn[0] >= P.t_end) {
-            // Land on t = t_end with the cubic Hermite interpolant of t(lambda);
-            // positions use dx/dlambda = k, momenta use dk/dlambda = acc.
-            const double th = hermite_zero((double)x[0] - P.t_end, (double)k[0], (double)xn[0] - P.t_end,
-                                           (double)kn[0], h);
-            TS xl[4], kl[4];
-#pragma unroll
+    #pragma unroll
             for (int c = 0; c < 4; ++c) {
-              xl[c] = (TS)herm(th, (double)x[c], (double)k[c], (double)xn[c], (double)kn[c], h);
-              kl[c] = (TS)herm(th, (double)k[c], (double)a1[c], (double)kn[c], (double)a7[c], h);
+              x[c] = xn[c];
+              k[c] = kn[c];
+              a1[c] = a7[c];
             }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              xn[c] = xl[c];
-              kn[c] = kl[c];
+            r_cur = r_new;
+            rdot_cur = rdot_new;
+            if (status == KH_ACTIVE) {
+              h = h * (double)grow_factor<TS>(err2, raw, after_reject);
+              const double hm = P.hmax_coeff * hscale(kind, (double)r_cur);
+              h = h < hm ? h : hm;
+              after_reject = false;
+              if (steps >= P.max_steps) status = KH_MAX_STEPS;
             }
-            lam = lam_old + th * h;
-            status = KH_T_END;
+          } else {
+            ++nrej;
+            h = h * (double)shrink_factor<TS>(err2, raw);
+            after_reject = true;
+            // written so that a NaN step size also ends the ray
+            if (!(h >= 1e-12 * P.h_coeff * hscale(kind, (double)r_cur))) status = KH_FAILED;
           }
+          if (status == KH_ACTIVE && ++tries > P.max_tries) status = KH_MAX_STEPS;
+          if (status != KH_ACTIVE) retire();
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          x[c] = xn[c];
-          k[c] = kn[c];
-          a1[c] = a7[c];
+        const unsigned long long idle_now = __ballot(ray < 0);
+        bool service = idle_now == ~0ull || (cursor < parts && __popcll(idle_now) >= P.refill_min);
+        if (P.k_cross > 0) {
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          service = service || *cq_count > kQCap - 64;
         }
-        r_cur = r_new;
-        rdot_cur = rdot_new;
-        if (status == KH_ACTIVE) {
-          h = h * (double)grow_factor<TS>(err2, raw, after_reject);
-          const double hm = P.hmax_coeff * hscale(kind, (double)r_cur);
-          h = h < hm ? h : hm;
-          after_reject = false;
-          if (steps >= P.max_steps) status = KH_MAX_STEPS;
-        }
-      } else {
-        ++nrej;
-        h = h * (double)shrink_factor<TS>(err2, raw);
-        after_reject = true;
-        // written so that a NaN step size also ends the ray
-        if (!(h >= 1e-12 * P.h_coeff * hscale(kind, (double)r_cur))) status = KH_FAILED;
+        if (service) break;
       }
-      if (status == KH_ACTIVE && ++tries > P.max_tries) status = KH_MAX_STEPS;
+      continue;
     }
 
-    if (status != KH_ACTIVE) {
-      // ---- retire: write the ray back and free the lane ----
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        S.s[c * n + ray] = (double)x[c];
-        S.s[(4 + c) * n + ray] = (double)k[c];
-      }
-      S.h[ray] = h;
-      S.lam[ray] = lam;
-      // the finalize pass adds atan2(y, x) to the winding part and clears the
-      // flags; without crossings the azimuth is not tracked and phi is left as is
-      if (P.k_cross > 0) S.phi[ray] = (2.0 * M_PI) * wind;
-      S.status[ray] = status | kRetired | (P.k_cross > 0 ? kPhiPending : 0);
-      S.n_acc[ray] = nacc;
-      S.n_rej[ray] = nrej;
-      if (S.n_cross) S.n_cross[ray] = ncross;
-      ray = -1;
-    }
+    if (status != KH_ACTIVE) retire();
   }
   if (P.k_cross > 0) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
