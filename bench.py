@@ -46,9 +46,9 @@ def kernel_source_hash():
 # (FETCH_SIZE, WRITE_SIZE, calibrated against a plain copy) and hardware FP64
 # FLOP per launch (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes), valid only for the
 # kernel source they were taken on.
-PROFILED = {"source_hash": "2d70ae41a0c952d0",
-            "traffic_bytes": (121587.125 * 2.0 + 323664.375 * 1.0) * 1024,
-            "hw_fp64_flops": 6203319763.0 * 64}
+PROFILED = {"source_hash": "3939c77042a60ccc",
+            "traffic_bytes": (120206.5625 * 2.0 + 309798.4375 * 1.0) * 1024,
+            "hw_fp64_flops": 6337090547.0 * 64}
 
 
 def algorithmic_flops(K, stats, n_rays, method, form):
@@ -344,6 +344,31 @@ def cpu_baseline(args):
                        f"rtol 1e-8, {t_total:.1f} s wall")
 
 
+def surrogate_image_only():
+    """The surrogate image kernel alone (timing and counters do not depend on
+    the weights; the fallback count does)."""
+    import torch
+
+    import paper_1706_07062_amd as K
+    from paper_1706_07062_amd import surrogate as SU, workloads as W
+
+    torch.cuda.set_device(0)
+    ctx = K.Context(0)
+    sur = SU.Surrogate(ctx, seed=0)
+    cam = W.surrogate_eval_camera()
+    ms = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, _, cnt = sur.image(cam, 0.2)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    log(f"surrogate image {cam.width}x{cam.height}: {', '.join(f'{m:.2f}' for m in ms)} ms; "
+        f"fallback {int(cnt.item())}")
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -355,6 +380,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, help="MiB; plain copy before the run (counter reference)")
     ap.add_argument("--surrogate-rays", type=int, default=10_000_000)
     ap.add_argument("--surrogate-steps", type=int, default=8000)
+    ap.add_argument("--surrogate-image-only", action="store_true",
+                    help="only the network's 4096^2 image, three times, with untrained seed-0 weights (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the integrator shards by ray range with no exchange on the hot "
@@ -362,6 +389,9 @@ def main():
         sys.exit(2)
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
+    if args.surrogate_image_only:
+        surrogate_image_only()
+        return
     out, _ = run_gpu(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args)
