@@ -123,8 +123,9 @@ typedef struct {
   int32_t block_size;   /* threads per block: 64, 128, 192 or 256; 0 = 256 */
   int32_t grid_blocks;  /* persistent grid size; 0 = fill the device from the occupancy query */
   int32_t refill_min;   /* a wave refills once at least this many lanes are idle (1..64); 0 = 16 */
-  int32_t waves_per_eu; /* register budget of the kernel variant: 0 or 1 = compiler's choice; DOPRI5 with
-                           the factored form also has 3 and 4 (FP64 / mixed) and 4 and 5 (FP32) */
+  int32_t waves_per_eu; /* register budget of the kernel variant (minimum waves per SIMD): 1 = two or more
+                           waves; DOPRI5 with the factored form also has 3 and 4 (FP64 / mixed) and 4 and 5
+                           (FP32); 0 = default (3 for mixed-precision DOPRI5, else 1) */
   int32_t queue_parts;  /* work-queue partitions of the ray range (1..8); 0 = 8, one per XCD: chunks of 8192
                            ids are dealt round-robin to the partitions, a wave starts on its XCD's partition
                            and steals from the others when it is drained */
