@@ -28,7 +28,7 @@ _LIB = os.path.join(_HERE, "libkerr_oracle.so")
 
 ACTIVE, CAPTURED, ESCAPED, T_END, MAX_STEPS, FAILED = range(6)
 NULL, TIMELIKE = 0, 1
-RK4, DOPRI5 = 0, 1
+RK4, DOPRI5, DOPRI5_T = 0, 1, 2  # DOPRI5_T: Dormand-Prince in coordinate time
 
 
 def build(force: bool = True) -> str:

@@ -259,14 +259,15 @@ double redshift(double r, double xi, double a) {
 // ----------------------------------------------------------------------------
 enum { ST_ACTIVE = 0, ST_CAPTURED = 1, ST_ESCAPED = 2, ST_T_END = 3, ST_MAX_STEPS = 4, ST_FAILED = 5 };
 enum { KIND_NULL = 0, KIND_TIMELIKE = 1 };
-enum { M_RK4 = 0, M_DOPRI5 = 1 };
+enum { M_RK4 = 0, M_DOPRI5 = 1, M_DOPRI5_T = 2 };
 
 }  // namespace
 
 extern "C" {
 
 typedef struct {
-  int32_t method;     // 0 = classic RK4 with h = h_coeff * r; 1 = Dormand-Prince 5(4)
+  int32_t method;     // 0 = classic RK4 with h = h_coeff * r; 1 = Dormand-Prince 5(4);
+                      // 2 = Dormand-Prince 5(4) in coordinate time (Sec. 2.2, eq:geo_t)
   int32_t k_cross;    // crossing slots per geodesic (0 disables crossing records)
   double h_coeff;     // RK4 step and DOPRI5 initial step coefficient
   double rtol, atol;  // DOPRI5 tolerances
@@ -546,6 +547,165 @@ void run_dopri5(const oracle_params& p, const Geo& G, Ray& R) {
   }
 }
 
+// ----------------------------------------------------------------------------
+// Coordinate-time integration (Sec. 2.2, the coordinate-time subsection):
+// with v^mu = dx^mu/dt (v^0 = 1) the spatial equations are
+//     dv^i/dt = -Gamma^i_{ab} v^a v^b + Gamma^0_{ab} v^a v^b v^i,
+// the paper's first display there, written out with the same Christoffel
+// symbols as eq:geo.  The state is the six numbers (x^i, v^i) and t is the
+// independent variable.  Dormand-Prince 5(4) as above, the RMS error norm over
+// the six components, the same controller, step scale and termination rules.
+// A target time t_end is hit exactly: the step is clipped to t_end - t.
+// On exit the state is returned in the affine form (x^mu, k^mu) with
+// k^mu = k^0 (1, v^i); k^0 follows from the conserved energy
+// E = -k_t = -k^0 (g_{0a} v^a) of the entry state, so E is preserved exactly
+// and the other constants (L_z, Q, mu^2) measure the drift.  The affine
+// parameter is not advanced.
+// ----------------------------------------------------------------------------
+void deriv_ct(double a, const double y[6], double dy[6]) {
+  const double x[4] = {0.0, y[0], y[1], y[2]};
+  const double v[4] = {1.0, y[3], y[4], y[5]};
+  double acc[4];
+  geodesic_rhs(a, x, v, acc);  // acc^mu = -Gamma^mu_{ab} v^a v^b
+  for (int i = 0; i < 3; ++i) {
+    dy[i] = y[3 + i];
+    dy[3 + i] = acc[1 + i] - acc[0] * y[3 + i];
+  }
+}
+
+double dopri5_attempt6(double a, const double y[6], const double f1[6], double h, double rtol, double atol,
+                       double y5[6], double f7[6]) {
+  double f2[6], f3[6], f4[6], f5[6], f6[6], t[6];
+  for (int c = 0; c < 6; ++c) t[c] = y[c] + h * (A21 * f1[c]);
+  deriv_ct(a, t, f2);
+  for (int c = 0; c < 6; ++c) t[c] = y[c] + h * (A31 * f1[c] + A32 * f2[c]);
+  deriv_ct(a, t, f3);
+  for (int c = 0; c < 6; ++c) t[c] = y[c] + h * (A41 * f1[c] + A42 * f2[c] + A43 * f3[c]);
+  deriv_ct(a, t, f4);
+  for (int c = 0; c < 6; ++c) t[c] = y[c] + h * (A51 * f1[c] + A52 * f2[c] + A53 * f3[c] + A54 * f4[c]);
+  deriv_ct(a, t, f5);
+  for (int c = 0; c < 6; ++c)
+    t[c] = y[c] + h * (A61 * f1[c] + A62 * f2[c] + A63 * f3[c] + A64 * f4[c] + A65 * f5[c]);
+  deriv_ct(a, t, f6);
+  for (int c = 0; c < 6; ++c) y5[c] = y[c] + h * (B1 * f1[c] + B3 * f3[c] + B4 * f4[c] + B5 * f5[c] + B6 * f6[c]);
+  deriv_ct(a, y5, f7);
+  double s = 0.0;
+  for (int c = 0; c < 6; ++c) {
+    double y4 = y[c] + h * (S1 * f1[c] + S3 * f3[c] + S4 * f4[c] + S5 * f5[c] + S6 * f6[c] + S7 * f7[c]);
+    double sc = atol + rtol * std::max(std::fabs(y[c]), std::fabs(y5[c]));
+    double e = (y5[c] - y4) / sc;
+    s += e * e;
+  }
+  return std::sqrt(s / 6.0);
+}
+
+// The 8-slot forms used by the shared crossing and termination helpers:
+// Y = (t, x^i, 1, v^i) and its t-derivative (1, v^i, 0, dv^i/dt).
+void to8(double t, const double y[6], double Y[8]) {
+  Y[0] = t;
+  Y[4] = 1.0;
+  for (int i = 0; i < 3; ++i) {
+    Y[1 + i] = y[i];
+    Y[5 + i] = y[3 + i];
+  }
+}
+void to8d(const double f[6], double F[8]) {
+  F[0] = 1.0;
+  F[4] = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    F[1 + i] = f[i];
+    F[5 + i] = f[3 + i];
+  }
+}
+
+void run_dopri5_ct(const oracle_params& p, const Geo& G, Ray& R) {
+  const double a = G.a_chart;
+  double kl[4];
+  lower(a, R.y, R.y + 4, kl);
+  const double E0 = -kl[0];
+  double t = R.y[0];
+  double y[6] = {R.y[1], R.y[2], R.y[3], R.y[5] / R.y[4], R.y[6] / R.y[4], R.y[7] / R.y[4]};
+  double f1[6];
+  deriv_ct(a, y, f1);
+  double Y[8];
+  to8(t, y, Y);
+  double h = p.h_coeff * hscale(G.kind, radius(a, Y));
+  h = std::min(h, p.hmax_coeff * hscale(G.kind, radius(a, Y)));
+  bool after_reject = false;
+  int64_t steps = 0, attempts = 0;
+  R.status = ST_ACTIVE;
+  if (p.t_end > 0.0 && t >= p.t_end) R.status = ST_T_END;  // already there: no step
+  while (R.status == ST_ACTIVE) {
+    const bool landing = p.t_end > 0.0 && t + h >= p.t_end;
+    const double hs = landing ? p.t_end - t : h;
+    double y5[6], f7[6];
+    double err = dopri5_attempt6(a, y, f1, hs, p.rtol, p.atol, y5, f7);
+    ++attempts;
+    if (err <= 1.0) {
+      double Y0[8], F0[8], Y1[8], F1[8];
+      to8(t, y, Y0);
+      to8d(f1, F0);
+      t = landing ? p.t_end : t + hs;
+      std::memcpy(y, y5, sizeof y);
+      std::memcpy(f1, f7, sizeof f1);
+      to8(t, y, Y1);
+      to8d(f1, F1);
+      R.nacc += 1;
+      ++steps;
+      bool bad = std::isnan(t);
+      for (int c = 0; c < 6; ++c) bad = bad || std::isnan(y[c]);
+      int32_t st = ST_ACTIVE;
+      if (bad) {
+        st = ST_FAILED;
+      } else {
+        if (p.k_cross > 0) {
+          double phi0 = R.phi;
+          R.phi = phi0 + std::atan2(Y0[1] * Y1[2] - Y0[2] * Y1[1], Y0[1] * Y1[1] + Y0[2] * Y1[2]);
+          detect_crossing(p, G, R, Y0, F0, Y1, F1, hs, phi0);
+        }
+        st = check_end(p, G, Y1);
+        if (st == ST_ACTIVE && landing) st = ST_T_END;
+      }
+      if (st != ST_ACTIVE) {
+        R.status = st;
+        break;
+      }
+      h = hs * grow_factor(err, after_reject);
+      h = std::min(h, p.hmax_coeff * hscale(G.kind, radius(a, Y1)));
+      after_reject = false;
+      if (steps >= p.max_steps) {
+        R.status = ST_MAX_STEPS;
+        break;
+      }
+    } else {
+      R.nrej += 1;
+      h = hs * shrink_factor(err);
+      after_reject = true;
+      double Yc[8];
+      to8(t, y, Yc);
+      if (!(h >= 1e-12 * p.h_coeff * hscale(G.kind, radius(a, Yc)))) {  // also ends a NaN step
+        R.status = ST_FAILED;
+        break;
+      }
+    }
+    if (attempts > 4 * p.max_steps + 1000) {
+      R.status = ST_MAX_STEPS;
+      break;
+    }
+  }
+  // back to (x^mu, k^mu): k^0 from the conserved energy of the entry state
+  double Yv[8];
+  to8(t, y, Yv);
+  lower(a, Yv, Yv + 4, kl);  // covariant components of (1, v)
+  const double k0 = E0 / (-kl[0]);
+  R.y[0] = t;
+  for (int i = 0; i < 3; ++i) {
+    R.y[1 + i] = y[i];
+    R.y[5 + i] = k0 * y[3 + i];
+  }
+  R.y[4] = k0;
+}
+
 template <class Fn>
 void parallel_chunks(int64_t n, int nthreads, Fn&& fn) {
   if (nthreads <= 0) nthreads = (int)std::max(1u, std::thread::hardware_concurrency());
@@ -676,7 +836,7 @@ int oracle_integrate(const oracle_params* p, int64_t n, double* s, const double*
                      double* lam, double* phi, int32_t* status, int32_t* n_acc, int32_t* n_rej, double* cross,
                      int32_t* n_cross, double* c0, double* c1, int32_t nthreads) {
   if (!p || n < 0) return -1;
-  if (p->method != M_RK4 && p->method != M_DOPRI5) return -1;
+  if (p->method != M_RK4 && p->method != M_DOPRI5 && p->method != M_DOPRI5_T) return -1;
   parallel_chunks(n, nthreads, [&](int64_t i) {
     Geo G;
     G.kind = kind[i];
@@ -699,6 +859,8 @@ int oracle_integrate(const oracle_params* p, int64_t n, double* s, const double*
     if (R.status == ST_ACTIVE) {
       if (p->method == M_RK4)
         run_rk4(*p, G, R);
+      else if (p->method == M_DOPRI5_T)
+        run_dopri5_ct(*p, G, R);
       else
         run_dopri5(*p, G, R);
     }

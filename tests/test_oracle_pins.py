@@ -546,3 +546,57 @@ def test_t_end_landing():
     assert abs(out["s"][0, 0] - 1234.5) <= 1e-12 * 1234.5
     d = np.abs(out["c1"] - out["c0"]) / np.maximum(np.abs(out["c0"]), 1.0)
     assert d.max() < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Coordinate-time integration (the coordinate-time subsection of Sec. 2.2):
+# the six-variable state (x^i, v^i = dx^i/dt) with t as independent variable.
+# ---------------------------------------------------------------------------
+def test_coordinate_time_circular_orbit_frequency():
+    """In coordinate time a circular equatorial orbit keeps its radius and
+    turns at exactly Omega = 1/(r^{3/2} + a) per unit t: three periods end on
+    the starting azimuth (the Cartesian azimuth differs from the spheroidal
+    one by a constant on a circle)."""
+    for a, r in ((0.0, 8.0), (0.5, 6.0), (0.998, 3.0)):
+        init = _circular(a, r)
+        T = 2 * np.pi / cf.omega_kepler(r, a)
+        p = O.Params(method=O.DOPRI5_T, rtol=1e-10, atol=1e-10, t_end=3 * T, r_escape=1e4)
+        out = O.integrate(init, p)
+        assert out["status"][0] == O.T_END
+        s = out["s"][:, 0]
+        assert s[0] == 3 * T  # the last step is clipped onto t_end exactly
+        assert O.radius(a, *s[1:4]) == pytest.approx(r, rel=1e-7)
+        assert abs(np.arctan2(s[2], s[1])) < 1e-6
+        # the energy is restored exactly (it fixes k^0); L_z and mu^2 drift at the tolerance
+        assert out["c1"][0, 0] == pytest.approx(out["c0"][0, 0], rel=1e-14)
+        assert out["c1"][1, 0] == pytest.approx(out["c0"][1, 0], rel=1e-8)
+        assert out["c1"][3, 0] == pytest.approx(out["c0"][3, 0], rel=1e-8)
+
+
+def test_coordinate_time_agrees_with_affine_integration():
+    """The two formulations integrate the same curve: particles landed on the
+    same t_end and photons scattered to the same escape direction agree to
+    the tolerance, though their step sequences differ completely."""
+    a = 0.9
+    # time-like: a tilted, slightly eccentric orbit
+    init = _circular(a, 9.0, vz=0.02)
+    pa = O.Params(method=O.DOPRI5, rtol=1e-10, atol=1e-10, t_end=700.0, r_escape=1e4)
+    pt = O.Params(method=O.DOPRI5_T, rtol=1e-10, atol=1e-10, t_end=700.0, r_escape=1e4)
+    oa, ot = O.integrate(init, pa), O.integrate(init, pt)
+    assert oa["status"][0] == ot["status"][0] == O.T_END
+    np.testing.assert_allclose(ot["s"][:4, 0], oa["s"][:4, 0], rtol=1e-7, atol=1e-7)
+    np.testing.assert_allclose(ot["s"][4:, 0], oa["s"][4:, 0], rtol=1e-6, atol=1e-8)
+    # null: image rays passing at a few impact parameters
+    rays = O.camera_rays(a, 1000.0, np.radians(60.0), -12.0, 12.0, -12.0, 12.0, 9, 9)
+    pa = O.Params(method=O.DOPRI5, rtol=1e-10, atol=1e-10)
+    pt = O.Params(method=O.DOPRI5_T, rtol=1e-10, atol=1e-10)
+    oa, ot = O.integrate(rays, pa), O.integrate(rays, pt)
+    assert np.array_equal(oa["status"], ot["status"])
+    esc = oa["status"] == O.ESCAPED
+    assert esc.sum() >= 40
+    da = oa["s"][5:8, esc] / np.linalg.norm(oa["s"][5:8, esc], axis=0)
+    dt = ot["s"][5:8, esc] / np.linalg.norm(ot["s"][5:8, esc], axis=0)
+    assert np.abs(da - dt).max() < 1e-6
+    # the escaped photon's k in coordinate time is rescaled to the entry energy
+    np.testing.assert_allclose(ot["c1"][0, esc], ot["c0"][0, esc], rtol=1e-13)
+    np.testing.assert_allclose(ot["c1"][3, esc], 0.0, atol=1e-8)  # still null
