@@ -58,7 +58,7 @@ enum {
  * ingoing chart); time-like geodesics run forward in the chart with spin +a. */
 enum { KH_NULL = 0, KH_TIMELIKE = 1 };
 
-enum { KH_RK4 = 0, KH_DOPRI5 = 1 };              /* kh_params.method */
+enum { KH_RK4 = 0, KH_DOPRI5 = 1, KH_DOPRI5_T = 2 }; /* kh_params.method */
 enum { KH_P64 = 0, KH_P32 = 1, KH_PMIXED = 2 };  /* kh_params.precision */
 enum { KH_RHS_FACTORED = 0, KH_RHS_PAPER = 1 };  /* kh_params.rhs_form */
 
@@ -108,7 +108,8 @@ typedef struct {
  * h_coeff 0.01, rtol = atol = 1e-8, hmax_coeff 0.1, r_h_factor 1.01,
  * r_escape 1000, t_end 0 (off), r_fp64 3, max_steps 1e6. */
 typedef struct {
-  int32_t method;    /* KH_RK4 (fixed step h = h_coeff * r) or KH_DOPRI5 */
+  int32_t method;    /* KH_RK4 (fixed step h = h_coeff * r), KH_DOPRI5, or KH_DOPRI5_T: Dormand-Prince in
+                        coordinate time (below) */
   int32_t precision; /* KH_P64, KH_P32 (rtol, atol raised to >= 1e-6), KH_PMIXED */
   int32_t rhs_form;  /* KH_RHS_FACTORED (default) or KH_RHS_PAPER */
   int32_t k_cross;   /* crossing slots to fill, 0..state.k_cross */
@@ -131,7 +132,18 @@ typedef struct {
                            and steals from the others when it is drained */
   int32_t reserved;
 } kh_params;
-/* scale(r) = r for null geodesics and r^{3/2} for time-like ones.  DOPRI5
+/* KH_DOPRI5_T (the coordinate-time subsection of Sec. 2.2): the six-variable
+ * state (x^i, v^i = dx^i/dt) is integrated in t with dv^i/dt = a^i - a^0 v^i,
+ * where a^mu is the affine right-hand side at k = (1, v).  Same tableau and
+ * controller; the error norm is the RMS over the six components; h is a
+ * coordinate-time step.  With t_end > 0 the step that would pass t_end is
+ * clipped onto it (status KH_T_END, x^0 == t_end exactly).  The state is
+ * read and written in the affine form: k^mu = k^0 (1, v^i) with k^0 fixed by
+ * the energy E = -k_t of the state the call started from (E is kept exactly;
+ * L_z, Q and mu^2 in c1 show the drift).  lam is not advanced.  Factored RHS
+ * only.
+ *
+ * scale(r) = r for null geodesics and r^{3/2} for time-like ones.  DOPRI5
  * controller: accept if err <= 1 (err = RMS over the 8 components of
  * (y5 - y4) / (atol + rtol max(|y_n|, |y_n+1|))), next step
  * h min(5, max(0.2, 0.9 err^{-1/5})) with no growth right after a rejection,

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libkerrhip.so")
 KH_OK, KH_EINVAL, KH_EHIP, KH_EUNSUPPORTED, KH_ENOMEM = 0, -1, -2, -3, -4
 ACTIVE, CAPTURED, ESCAPED, T_END, MAX_STEPS, FAILED = range(6)
 NULL, TIMELIKE = 0, 1
-RK4, DOPRI5 = 0, 1
+RK4, DOPRI5, DOPRI5_T = 0, 1, 2
 P64, P32, PMIXED = 0, 1, 2
 RHS_FACTORED, RHS_PAPER = 0, 1
 

@@ -204,7 +204,7 @@ __device__ inline void flush_crossings(double* q, int* qcnt, int count, const KS
 
 // ---------------------------------------------------------------------------
 // Persistent integrate kernel.
-// METHOD: KH_RK4 / KH_DOPRI5.  PREC: KH_P64 / KH_P32 / KH_PMIXED.
+// METHOD: KH_RK4 / KH_DOPRI5 / KH_DOPRI5_T (coordinate time).  PREC: KH_P64 / KH_P32 / KH_PMIXED.
 // FORM: right-hand-side evaluation (KH_RHS_FACTORED / KH_RHS_PAPER).
 // ---------------------------------------------------------------------------
 // WPE: minimum waves per SIMD the register allocation must allow (1 = no limit).
@@ -234,10 +234,14 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
   int cursor = 0;  // partitions this wave has seen drained (wave-uniform)
   bool fresh = false;
 
+  // Coordinate-time integration: the state is (t, x^i) and (1, v^i), v = dx/dt;
+  // k keeps the slot layout with k[0] = 1, a1[0] = 0.  E0 = -k_t of the entry
+  // state restores k^mu = k^0 (1, v) at retirement.
+  constexpr bool CT = METHOD == KH_DOPRI5_T;
   TS x[4], k[4], a1[4];
   TS r_cur = TS(0), rdot_cur = TS(0);
   TS a_c = TS(0);
-  double h = 0.0, lam = 0.0, rcap = 0.0;
+  double h = 0.0, lam = 0.0, rcap = 0.0, E0 = 0.0;
   int kind = 0, nacc = 0, nrej = 0, ncross = 0, status = KH_ACTIVE;
   // Unwrapped azimuth = atan2(y, x) + 2 pi * wind: wind counts passages across
   // the negative x axis, so no arctangent is needed on ordinary steps.
@@ -247,10 +251,26 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
 
   // ---- retire: write the ray back and free the lane ----
   auto retire = [&]() {
+    if (CT) {
+      // k^0 = E0 / E(1, v): the energy of the entry state is kept exactly
+      double xd[4], vd[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      S.s[c * n + ray] = (double)x[c];
-      S.s[(4 + c) * n + ray] = (double)k[c];
+      for (int c = 0; c < 4; ++c) {
+        xd[c] = (double)x[c];
+        vd[c] = (double)k[c];
+      }
+      const double k0 = E0 / energy((double)a_c, xd, vd);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        S.s[c * n + ray] = xd[c];
+        S.s[(4 + c) * n + ray] = k0 * vd[c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        S.s[c * n + ray] = (double)x[c];
+        S.s[(4 + c) * n + ray] = (double)k[c];
+      }
     }
     S.h[ray] = h;
     S.lam[ray] = lam;
@@ -288,6 +308,19 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
           kind = S.kind[id];
           const double a_phys = S.spin[id];
           a_c = (TS)(kind == KH_NULL ? -a_phys : a_phys);
+          if (CT) {
+            double xd[4], kd[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              xd[c] = S.s[c * n + id];
+              kd[c] = S.s[(4 + c) * n + id];
+            }
+            E0 = energy(kind == KH_NULL ? -a_phys : a_phys, xd, kd);
+            const double ik0 = 1.0 / kd[0];
+            k[0] = TS(1);
+#pragma unroll
+            for (int c = 1; c < 4; ++c) k[c] = (TS)(kd[c] * ik0);
+          }
           h = S.h[id];
           lam = S.lam[id];
           // phi = atan2(y, x) + 2 pi wind on entry; a coarse azimuth recovers wind
@@ -315,12 +348,12 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
 
     // ---- first-stage acceleration of a freshly loaded ray (idle lanes have fresh = false) ----
     if (fresh || METHOD == KH_RK4) {
-      const Accel<TS> ra = rhs<FORM, TS>(a_c, x, k);
+      const Accel<TS> ra = CT ? rhs_ct<FORM, TS>(a_c, x, k) : rhs<FORM, TS>(a_c, x, k);
 #pragma unroll
       for (int c = 0; c < 4; ++c) a1[c] = ra.a[c];
       r_cur = ra.r;
       rdot_cur = ra.rdot;
-      if (METHOD == KH_DOPRI5 && fresh && !(h > 0.0)) {
+      if (METHOD != KH_RK4 && fresh && !(h > 0.0)) {
         h = P.h_coeff * hscale(kind, (double)r_cur);
         const double hm = P.hmax_coeff * hscale(kind, (double)r_cur);
         h = h < hm ? h : hm;
@@ -370,13 +403,16 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
       while (true) {
         if (ray >= 0) {
           TS xn[4], kn[4], a7[4], r_new, rdot_new;
-          const TS hs = (TS)h;
+          // coordinate time: a step that would pass t_end is clipped onto it
+          const bool landing = CT && P.t_end > 0.0 && (double)x[0] + h >= P.t_end;
+          const double hd = landing ? P.t_end - (double)x[0] : h;
+          const TS hs = (TS)hd;
           const TS rtol = (TS)P.rtol, atol = (TS)P.atol;
           TS err2;  // squared RMS error norm
           if (PREC == KH_PMIXED && __ballot(r_cur < (TS)P.r_fp64) == 0ull)
-            err2 = dp5_attempt<FORM, TS, TF>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
+            err2 = dp5_attempt<FORM, TS, TF, CT>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
           else
-            err2 = dp5_attempt<FORM, TS, TS>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
+            err2 = dp5_attempt<FORM, TS, TS, CT>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
 
           const TS raw = TS(0.9) * kpow_m1_10(err2);
           if (err2 <= TS(1)) {
@@ -386,7 +422,11 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
     #pragma unroll
             for (int c = 0; c < 4; ++c) bad = bad || (xn[c] != xn[c]) || (kn[c] != kn[c]);
             const double lam_old = lam;
-            lam += h;
+            if (CT) {
+              if (landing) xn[0] = (TS)P.t_end;  // the clipped step ends on t_end exactly
+            } else {
+              lam += h;  // the affine parameter is not tracked in coordinate time
+            }
             if (bad) {
               status = KH_FAILED;
             } else {
@@ -413,7 +453,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
                     cq[QKX1 * kQCap + j] = (double)kn[1];
                     cq[QKY1 * kQCap + j] = (double)kn[2];
                     cq[QKZ1 * kQCap + j] = (double)kn[3];
-                    cq[QH * kQCap + j] = h;
+                    cq[QH * kQCap + j] = hd;
                     cq[QAC * kQCap + j] = (double)a_c;
                     cq[QWIND * kQCap + j] = (double)wind0;
                     cq[QTAG * kQCap + j] = (double)((((int64_t)ray * 8 + ncross) << 1) | (kind == KH_NULL ? 0 : 1));
@@ -425,7 +465,9 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
                 status = KH_CAPTURED;
               else if ((double)r_new > P.r_escape && rdot_new > TS(0))
                 status = KH_ESCAPED;
-              else if (P.t_end > 0.0 && (double)xn[0] >= P.t_end) {
+              else if (CT && landing)
+                status = KH_T_END;
+              else if (!CT && P.t_end > 0.0 && (double)xn[0] >= P.t_end) {
                 // Land on t = t_end with the cubic Hermite interpolant of t(lambda);
                 // positions use dx/dlambda = k, momenta use dk/dlambda = acc.
                 const double th = hermite_zero((double)x[0] - P.t_end, (double)k[0], (double)xn[0] - P.t_end,
@@ -454,7 +496,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
             r_cur = r_new;
             rdot_cur = rdot_new;
             if (status == KH_ACTIVE) {
-              h = h * (double)grow_factor<TS>(err2, raw, after_reject);
+              h = hd * (double)grow_factor<TS>(err2, raw, after_reject);
               const double hm = P.hmax_coeff * hscale(kind, (double)r_cur);
               h = h < hm ? h : hm;
               after_reject = false;
@@ -462,7 +504,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
             }
           } else {
             ++nrej;
-            h = h * (double)shrink_factor<TS>(err2, raw);
+            h = hd * (double)shrink_factor<TS>(err2, raw);
             after_reject = true;
             // written so that a NaN step size also ends the ray
             if (!(h >= 1e-12 * P.h_coeff * hscale(kind, (double)r_cur))) status = KH_FAILED;
@@ -908,6 +950,10 @@ void* pick_kernel(int method, int prec, int form, int wpe) {
   KH_PICK(KH_DOPRI5, KH_P32, KH_RHS_FACTORED, 5)
   KH_PICK(KH_DOPRI5, KH_PMIXED, KH_RHS_FACTORED, 3)
   KH_PICK(KH_DOPRI5, KH_PMIXED, KH_RHS_FACTORED, 4)
+  KH_PICK(KH_DOPRI5_T, KH_P64, KH_RHS_FACTORED, 1)
+  KH_PICK(KH_DOPRI5_T, KH_P32, KH_RHS_FACTORED, 1)
+  KH_PICK(KH_DOPRI5_T, KH_PMIXED, KH_RHS_FACTORED, 1)
+  KH_PICK(KH_DOPRI5_T, KH_PMIXED, KH_RHS_FACTORED, 3)
 #undef KH_PICK
   return nullptr;
 }
@@ -1139,13 +1185,14 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   if (!ctx) return KH_EINVAL;
   g_skip_ptr_query = capturing(stream);
   if (!p) return fail(ctx, KH_EINVAL, "params is NULL");
-  if (p->method != KH_RK4 && p->method != KH_DOPRI5) return fail(ctx, KH_EINVAL, "unknown method");
+  if (p->method != KH_RK4 && p->method != KH_DOPRI5 && p->method != KH_DOPRI5_T)
+    return fail(ctx, KH_EINVAL, "unknown method");
   if (p->precision != KH_P64 && p->precision != KH_P32 && p->precision != KH_PMIXED)
     return fail(ctx, KH_EINVAL, "unknown precision");
   if (p->rhs_form != KH_RHS_FACTORED && p->rhs_form != KH_RHS_PAPER) return fail(ctx, KH_EINVAL, "unknown rhs_form");
   if (!(p->h_coeff > 0.0) || !(p->r_h_factor > 0.0) || !(p->r_escape > 0.0) || p->max_steps < 1)
     return fail(ctx, KH_EINVAL, "need h_coeff, r_h_factor, r_escape > 0 and max_steps >= 1");
-  if (p->method == KH_DOPRI5 && (!(p->rtol > 0.0) || !(p->atol > 0.0) || !(p->hmax_coeff > 0.0)))
+  if (p->method != KH_RK4 && (!(p->rtol > 0.0) || !(p->atol > 0.0) || !(p->hmax_coeff > 0.0)))
     return fail(ctx, KH_EINVAL, "DOPRI5 needs rtol, atol, hmax_coeff > 0");
   if (p->k_cross < 0 || p->k_cross > 8) return fail(ctx, KH_EINVAL, "k_cross must be in [0, 8]");
   if (p->method == KH_RK4 && (p->k_cross > 0 || p->t_end > 0.0))
@@ -1189,7 +1236,7 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   // Default register budget: MIXED DOPRI5 runs faster at three waves per SIMD
   // (spilling a few registers) than at two; FP64 and FP32 do not gain.
   int wpe = p->waves_per_eu;
-  if (wpe == 0) wpe = (p->method == KH_DOPRI5 && p->precision == KH_PMIXED && p->rhs_form == KH_RHS_FACTORED) ? 3 : 1;
+  if (wpe == 0) wpe = (p->method != KH_RK4 && p->precision == KH_PMIXED && p->rhs_form == KH_RHS_FACTORED) ? 3 : 1;
   void* fn = pick_kernel(p->method, p->precision, p->rhs_form, wpe);
   if (!fn) return fail(ctx, KH_EUNSUPPORTED, "no kernel for this method / precision / rhs_form / waves_per_eu");
   // dynamic LDS: one crossing queue (kQFields x kQCap doubles + a counter) per wave
@@ -1309,14 +1356,18 @@ kh_status kh_rhs(kh_ctx* ctx, int32_t precision, int32_t rhs_form, const double*
 }
 
 kh_status kh_flops(int32_t method, int32_t rhs_form, kh_flop_counts* out) {
-  if (!out || (method != KH_RK4 && method != KH_DOPRI5) ||
-      (rhs_form != KH_RHS_FACTORED && rhs_form != KH_RHS_PAPER))
+  if (!out || (method != KH_RK4 && method != KH_DOPRI5 && method != KH_DOPRI5_T) ||
+      (rhs_form != KH_RHS_FACTORED && rhs_form != KH_RHS_PAPER) ||
+      (method == KH_DOPRI5_T && rhs_form != KH_RHS_FACTORED))
     return KH_EINVAL;
   Tally t_rhs, t_step;
   const Cnt x[4] = {Cnt(0.0), Cnt(7.0), Cnt(-3.0), Cnt(2.0)};
   const Cnt k[4] = {Cnt(1.2), Cnt(-0.6), Cnt(0.3), Cnt(-0.2)};
   g_tally = &t_rhs;
-  if (rhs_form == KH_RHS_FACTORED)
+  const Cnt v[4] = {Cnt(1.0), Cnt(-0.5), Cnt(0.25), Cnt(-0.15)};
+  if (method == KH_DOPRI5_T)
+    (void)rhs_ct<KH_RHS_FACTORED, Cnt>(Cnt(0.9), x, v);
+  else if (rhs_form == KH_RHS_FACTORED)
     (void)rhs<KH_RHS_FACTORED, Cnt>(Cnt(0.9), x, k);
   else
     (void)rhs<KH_RHS_PAPER, Cnt>(Cnt(0.9), x, k);
@@ -1324,7 +1375,12 @@ kh_status kh_flops(int32_t method, int32_t rhs_form, kh_flop_counts* out) {
   Cnt xn[4], kn[4], a7[4], r, rd;
   const Cnt a1[4] = {Cnt(0.01), Cnt(0.02), Cnt(-0.01), Cnt(0.005)};
   int n_rhs;
-  if (method == KH_DOPRI5) {
+  if (method == KH_DOPRI5_T) {
+    const Cnt a1t[4] = {Cnt(0.0), Cnt(0.02), Cnt(-0.01), Cnt(0.005)};
+    (void)dp5_attempt<KH_RHS_FACTORED, Cnt, Cnt, true>(Cnt(0.9), x, v, a1t, Cnt(0.1), Cnt(1e-8), Cnt(1e-8), xn, kn, a7,
+                                                        r, rd);
+    n_rhs = 6;
+  } else if (method == KH_DOPRI5) {
     if (rhs_form == KH_RHS_FACTORED)
       (void)dp5_attempt<KH_RHS_FACTORED, Cnt, Cnt>(Cnt(0.9), x, k, a1, Cnt(0.1), Cnt(1e-8), Cnt(1e-8), xn, kn, a7, r,
                                                    rd);

@@ -244,6 +244,31 @@ __host__ __device__ inline Accel<T> rhs(T a, const T x[4], const T k[4]) {
     return rhs_factored<T>(a, x, k);
 }
 
+// Coordinate-time form (Sec. 2.2, the coordinate-time subsection): with
+// v^mu = dx^mu/dt (v^0 = 1) the spatial equations are dv^i/dt = a^i - a^0 v^i,
+// where a^mu is the affine right-hand side evaluated at k = v (it is
+// quadratic in k, so the k^0 scale drops out).  Same radius and dr/dt.
+template <int FORM, typename T>
+__host__ __device__ inline Accel<T> rhs_ct(T a, const T x[4], const T v[4]) {
+  Accel<T> out = rhs<FORM, T>(a, x, v);
+  const T a0 = out.a[0];
+  out.a[0] = T(0);
+#pragma unroll
+  for (int i = 1; i < 4; ++i) out.a[i] = out.a[i] - a0 * v[i];
+  return out;
+}
+
+// Energy E = -k_t = k^0 - f K (K = k^0 + l_i k^i) in the chart of spin a.
+__host__ __device__ inline double energy(double a, const double x[4], const double k[4]) {
+  const double a2 = a * a;
+  const double r2 = ks_r2(a2, x[1], x[2], x[3]);
+  const double r = sqrt(r2);
+  const double iS = 1.0 / (r2 + a2);
+  const double f = 2.0 * r2 * r / (r2 * r2 + a2 * x[3] * x[3]);
+  const double l1 = (r * x[1] + a * x[2]) * iS, l2 = (r * x[2] - a * x[1]) * iS, l3 = x[3] / r;
+  return k[0] - f * (k[0] + l1 * k[1] + l2 * k[2] + l3 * k[3]);
+}
+
 // Null condition: k^0 = [f L + sqrt(1 - f + f L^2)] / (1 - f), L = l_i k^i with
 // |k^i| = 1 scaled out: for general spatial k, the future root of
 // (f - 1) k0^2 + 2 f L k0 + |k|^2 + f L^2 = 0.

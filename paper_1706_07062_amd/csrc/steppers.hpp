@@ -87,7 +87,10 @@ struct Conv {
 // Coefficients that are exactly zero (A A on the sub-diagonal, b_2, b A on the
 // sixth stage, e_2) are skipped at compile time: IEEE rules forbid the
 // compiler from dropping 0 * s itself.
-template <int FORM, typename TS, typename TR>
+// CTF: coordinate-time form (x = (t, x^i), k = (1, v^i), the right-hand side
+// rhs_ct; the t and v^0 slots have zero derivative and drop out of the norm,
+// which is then the RMS over the six evolved components).
+template <int FORM, typename TS, typename TR, bool CTF = false>
 __host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], const TS a1[4], TS h, TS rtol,
                                           TS atol, TS xn[4], TS kn[4], TS a7[4], TS& r_new, TS& rdot_new) {
   TS S[6][4];
@@ -117,7 +120,7 @@ __host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], 
                                             : x[c] + h * (TS(DP5.c[i]) * k[c]));
       K[c] = Conv<TS, TR>::to(hk ? k[c] + h * sk : k[c]);
     }
-    const Accel<TR> ra = rhs<FORM, TR>(ac, X, K);
+    const Accel<TR> ra = CTF ? rhs_ct<FORM, TR>(ac, X, K) : rhs<FORM, TR>(ac, X, K);
 #pragma unroll
     for (int c = 0; c < 4; ++c) S[i][c] = Conv<TS, TR>::from(ra.a[c]);
   }
@@ -146,7 +149,7 @@ __host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], 
       X[c] = Conv<TS, TR>::to(xn[c]);
       K[c] = Conv<TS, TR>::to(kn[c]);
     }
-    const Accel<TR> ra = rhs<FORM, TR>(ac, X, K);
+    const Accel<TR> ra = CTF ? rhs_ct<FORM, TR>(ac, X, K) : rhs<FORM, TR>(ac, X, K);
 #pragma unroll
     for (int c = 0; c < 4; ++c) a7[c] = Conv<TS, TR>::from(ra.a[c]);
     r_new = Conv<TS, TR>::from(ra.r);
@@ -178,7 +181,7 @@ __host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], 
     const TS qx = ex * krcp_est(sx), qk = ek * krcp_est(sk);
     s2 = s2 + qx * qx + qk * qk;
   }
-  return s2 * TS(0.125);
+  return s2 * (CTF ? TS(1.0 / 6.0) : TS(0.125));
 }
 
 // One classic RK4 step of length h from (x, k) with acceleration a1 = acc(x, k).
