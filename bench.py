@@ -155,9 +155,10 @@ def extras(args, ctx, K, W, torch):  # noqa: C901
     kc = [K.kh_camera(c.a, c.r_obs, c.incl, c.alpha_min, c.alpha_max, c.beta_min, c.beta_max, c.width, c.height)
           for c in cams]
     n = sum(c.n for c in cams)
-    for name, prec, tol in (("fp32", K.P32, 1e-6), ("mixed", K.PMIXED, 1e-8)):
+    for name, prec, tol, method in (("fp32", K.P32, 1e-6, K.DOPRI5), ("mixed", K.PMIXED, 1e-8, K.DOPRI5),
+                                    ("coordinate_time_fp64", K.P64, 1e-8, K.DOPRI5_T)):
         st = K.State(n, k_cross=4)
-        p = K.kh_default_params(k_cross=4, precision=prec, rtol=tol, atol=tol)
+        p = K.kh_default_params(k_cross=4, precision=prec, rtol=tol, atol=tol, method=method)
         ctx.kh_init_rays(kc, st)
         ctx.kh_integrate(p, st)
         torch.cuda.synchronize()
@@ -273,16 +274,19 @@ def batched_extra(ctx, K, W, torch):
 
 def particles_extra(ctx, K, W, torch):
     """2^20 time-like geodesics to t = 1e4 M: FP64 (rtol 1e-8) and FP32
-    (rtol 1e-6), constants-of-motion drift per particle."""
+    (rtol 1e-6), each with the affine parameter and in coordinate time,
+    constants-of-motion drift per particle."""
     pw = W.particles()
     n = len(pw["a"])
     t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()  # noqa: E731
     spin, x3, v3 = t(pw["a"]), t(pw["x3"]), t(pw["v3"])
     out = {}
     finals = {}
-    for name, prec, tol in (("fp64", K.P64, 1e-8), ("fp32", K.P32, 1e-6)):
+    for name, prec, tol, method in (("fp64", K.P64, 1e-8, K.DOPRI5), ("fp32", K.P32, 1e-6, K.DOPRI5),
+                                    ("fp64_coordinate_time", K.P64, 1e-8, K.DOPRI5_T),
+                                    ("fp32_coordinate_time", K.P32, 1e-6, K.DOPRI5_T)):
         st = K.State(n)
-        p = K.kh_default_params(precision=prec, rtol=tol, atol=tol, t_end=1e4, r_escape=1e4)
+        p = K.kh_default_params(precision=prec, rtol=tol, atol=tol, t_end=1e4, r_escape=1e4, method=method)
         ctx.kh_init_geodesics(K.TIMELIKE, spin, x3, v3, st)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -303,6 +307,10 @@ def particles_extra(ctx, K, W, torch):
     both = l64 & l32
     d = np.linalg.norm(s32[1:4, both] - s64[1:4, both], axis=0) / np.linalg.norm(s64[1:4, both], axis=0)
     out["fp32_vs_fp64_position"] = dict(median=float(np.median(d)), p99=float(np.quantile(d, 0.99)))
+    (sct, lct) = finals["fp64_coordinate_time"]
+    both = l64 & lct
+    d = np.linalg.norm(sct[1:4, both] - s64[1:4, both], axis=0) / np.linalg.norm(s64[1:4, both], axis=0)
+    out["coordinate_time_vs_affine_position"] = dict(median=float(np.median(d)), p99=float(np.quantile(d, 0.99)))
     return out
 
 
