@@ -93,6 +93,8 @@ def lib():
         L.oracle_timelike.argtypes = [pd, pd, pd, i64, pd, pd, pi32, pi32]
         L.oracle_integrate.argtypes = [P(_Params), i64, pd, pd, pi32, pd, pd, pi32, pi32, pi32, pd, pi32, pd, pd,
                                        i32]
+        L.oracle_integrate_out.argtypes = [P(_Params), i64, pd, pd, pi32, pd, pd, pi32, pi32, pi32, pd, pi32, pd,
+                                           pd, i32, pd, pd, i32]
         L.oracle_trajectory.argtypes = [P(_Params), d, pd, i64, pd]
         L.oracle_trajectory.restype = i64
         L.oracle_rhs.argtypes = [d, pd, pd, pd]
@@ -153,8 +155,11 @@ def timelike(a, x3, v3):
     return dict(s=s, spin=spin, kind=kind, status=status)
 
 
-def integrate(init: dict, params: Params, nthreads: int = 0) -> dict:
-    """Integrate every ACTIVE geodesic of ``init`` to termination."""
+def integrate(init: dict, params: Params, nthreads: int = 0, t_out=None) -> dict:
+    """Integrate every ACTIVE geodesic of ``init`` to termination.  With
+    ``t_out`` (ascending coordinate times) the result also holds ``s_out``
+    [n][len(t_out)][8]: the state at each time the geodesic reaches (NaN
+    elsewhere)."""
     s = np.array(init["s"], dtype=np.float64, order="C", copy=True)
     n = s.shape[1]
     spin = _f64(init["spin"])
@@ -170,14 +175,21 @@ def integrate(init: dict, params: Params, nthreads: int = 0) -> dict:
     c0 = np.zeros((4, n))
     c1 = np.zeros((4, n))
     cp = params.c()
-    rc = lib().oracle_integrate(C.byref(cp), n, _p(s, C.c_double), _p(spin, C.c_double), _p(kind, C.c_int32),
-                                _p(lam, C.c_double), _p(phi, C.c_double), _p(status, C.c_int32),
-                                _p(n_acc, C.c_int32), _p(n_rej, C.c_int32), _p(cross, C.c_double),
-                                _p(n_cross, C.c_int32), _p(c0, C.c_double), _p(c1, C.c_double), nthreads)
+    t_out = np.zeros(0) if t_out is None else _f64(t_out)
+    n_out = len(t_out)
+    s_out = np.full((n, max(n_out, 1), 8), np.nan)
+    rc = lib().oracle_integrate_out(C.byref(cp), n, _p(s, C.c_double), _p(spin, C.c_double), _p(kind, C.c_int32),
+                                    _p(lam, C.c_double), _p(phi, C.c_double), _p(status, C.c_int32),
+                                    _p(n_acc, C.c_int32), _p(n_rej, C.c_int32), _p(cross, C.c_double),
+                                    _p(n_cross, C.c_int32), _p(c0, C.c_double), _p(c1, C.c_double), n_out,
+                                    _p(t_out, C.c_double), _p(s_out, C.c_double), nthreads)
     if rc != 0:
         raise ValueError("oracle_integrate rejected its arguments")
-    return dict(s=s, lam=lam, phi=phi, status=status, n_acc=n_acc, n_rej=n_rej, cross=cross[:, :K],
-                n_cross=n_cross, c0=c0, c1=c1)
+    out = dict(s=s, lam=lam, phi=phi, status=status, n_acc=n_acc, n_rej=n_rej, cross=cross[:, :K],
+               n_cross=n_cross, c0=c0, c1=c1)
+    if n_out:
+        out["s_out"] = s_out
+    return out
 
 
 def trajectory(params: Params, spin_chart: float, y0, max_out: int = 100000) -> np.ndarray:

@@ -347,7 +347,23 @@ struct Ray {
   double lam, phi;
   int32_t status, nacc, nrej, ncross;
   double* cross;  // k_cross * 3
+  // dense output at coordinate times (method (ii) of Sec. 2.2): ascending
+  // targets t_out[0..n_out), states written to s_out[j][8], next target j_out
+  int32_t n_out = 0, j_out = 0;
+  const double* t_out = nullptr;
+  double* s_out = nullptr;
 };
+
+// First target at or after the entry time; a target equal to it takes the
+// entry state.
+void dense_out_start(Ray& R) {
+  if (R.n_out == 0) return;
+  while (R.j_out < R.n_out && R.t_out[R.j_out] < R.y[0]) ++R.j_out;
+  if (R.j_out < R.n_out && R.t_out[R.j_out] == R.y[0]) {
+    for (int c = 0; c < 8; ++c) R.s_out[8 * R.j_out + c] = R.y[c];
+    ++R.j_out;
+  }
+}
 
 bool any_nan(const double y[8]) {
   for (int c = 0; c < 8; ++c)
@@ -479,6 +495,7 @@ double shrink_factor(double err) { return std::isnan(err) ? 0.2 : std::max(0.2, 
 
 void run_dopri5(const oracle_params& p, const Geo& G, Ray& R) {
   const double a = G.a_chart;
+  dense_out_start(R);
   auto F = [a](const double* y, double* dy) { deriv(a, y, dy); };
   double f1[8];
   F(R.y, f1);
@@ -509,6 +526,16 @@ void run_dopri5(const oracle_params& p, const Geo& G, Ray& R) {
         double phi0 = R.phi;
         R.phi = phi0 + std::atan2(y0[1] * R.y[2] - y0[2] * R.y[1], y0[1] * R.y[1] + y0[2] * R.y[2]);
         detect_crossing(p, G, R, y0, f0, R.y, f1, h, phi0);
+      }
+      // dense output: every target time passed by this step, from the Hermite
+      // interpolant of t(lambda) (root) and of the state (never past t_end)
+      while (R.j_out < R.n_out && R.t_out[R.j_out] <= R.y[0] && !(p.t_end > 0.0 && R.t_out[R.j_out] > p.t_end)) {
+        const double tj = R.t_out[R.j_out];
+        double th = hermite_root(0, y0, f0, R.y, f1, h, tj);
+        double* o = R.s_out + 8 * R.j_out;
+        hermite_state(th, y0, f0, R.y, f1, h, o);
+        o[0] = tj;
+        ++R.j_out;
       }
       int32_t st = check_end(p, G, R.y);
       if (st == ST_ACTIVE && p.t_end > 0.0 && R.y[0] >= p.t_end) {
@@ -620,6 +647,7 @@ void to8d(const double f[6], double F[8]) {
 
 void run_dopri5_ct(const oracle_params& p, const Geo& G, Ray& R) {
   const double a = G.a_chart;
+  dense_out_start(R);
   double kl[4];
   lower(a, R.y, R.y + 4, kl);
   const double E0 = -kl[0];
@@ -662,6 +690,24 @@ void run_dopri5_ct(const oracle_params& p, const Geo& G, Ray& R) {
           double phi0 = R.phi;
           R.phi = phi0 + std::atan2(Y0[1] * Y1[2] - Y0[2] * Y1[1], Y0[1] * Y1[1] + Y0[2] * Y1[2]);
           detect_crossing(p, G, R, Y0, F0, Y1, F1, hs, phi0);
+        }
+        // dense output: in coordinate time the target sits at theta = (t_j - t0) / h;
+        // k^mu = k^0 (1, v) with k^0 from the entry energy, as on exit
+        while (R.j_out < R.n_out && R.t_out[R.j_out] <= t) {
+          const double tj = R.t_out[R.j_out];
+          double Yj[8];
+          hermite_state((tj - Y0[0]) / hs, Y0, F0, Y1, F1, hs, Yj);
+          Yj[0] = tj;
+          Yj[4] = 1.0;
+          double klj[4];
+          lower(a, Yj, Yj + 4, klj);
+          const double k0 = E0 / (-klj[0]);
+          double* o = R.s_out + 8 * R.j_out;
+          for (int c = 0; c < 4; ++c) {
+            o[c] = Yj[c];
+            o[4 + c] = k0 * Yj[4 + c];
+          }
+          ++R.j_out;
         }
         st = check_end(p, G, Y1);
         if (st == ST_ACTIVE && landing) st = ST_T_END;
@@ -829,14 +875,31 @@ int oracle_timelike(const double* a, const double* x3, const double* v3, int64_t
   return 0;
 }
 
+int oracle_integrate_out(const oracle_params* p, int64_t n, double* s, const double* spin, const int32_t* kind,
+                         double* lam, double* phi, int32_t* status, int32_t* n_acc, int32_t* n_rej, double* cross,
+                         int32_t* n_cross, double* c0, double* c1, int32_t n_out, const double* t_out,
+                         double* s_out, int32_t nthreads);
+
 // Integrate n geodesics from their current state.  s is [8][n]; cross is
 // [n][k_cross][3] = (r, phi, g); c0/c1 are [4][n] = (E, L_z, Q, mu^2) at the start
 // and at the end (may be NULL).  Geodesics whose status is not ACTIVE are skipped.
 int oracle_integrate(const oracle_params* p, int64_t n, double* s, const double* spin, const int32_t* kind,
                      double* lam, double* phi, int32_t* status, int32_t* n_acc, int32_t* n_rej, double* cross,
                      int32_t* n_cross, double* c0, double* c1, int32_t nthreads) {
-  if (!p || n < 0) return -1;
+  return oracle_integrate_out(p, n, s, spin, kind, lam, phi, status, n_acc, n_rej, cross, n_cross, c0, c1, 0, nullptr,
+                              nullptr, nthreads);
+}
+
+// The same, with dense output at the ascending coordinate times t_out[0..n_out):
+// s_out is [n][n_out][8] (x^mu, k^mu at t_out[j]; entries the call does not
+// reach are left as they are).  DOPRI5 methods only.
+int oracle_integrate_out(const oracle_params* p, int64_t n, double* s, const double* spin, const int32_t* kind,
+                         double* lam, double* phi, int32_t* status, int32_t* n_acc, int32_t* n_rej, double* cross,
+                         int32_t* n_cross, double* c0, double* c1, int32_t n_out, const double* t_out,
+                         double* s_out, int32_t nthreads) {
+  if (!p || n < 0 || n_out < 0 || (n_out > 0 && (!t_out || !s_out))) return -1;
   if (p->method != M_RK4 && p->method != M_DOPRI5 && p->method != M_DOPRI5_T) return -1;
+  if (n_out > 0 && p->method == M_RK4) return -1;
   parallel_chunks(n, nthreads, [&](int64_t i) {
     Geo G;
     G.kind = kind[i];
@@ -852,6 +915,9 @@ int oracle_integrate(const oracle_params* p, int64_t n, double* s, const double*
     R.ncross = 0;
     std::vector<double> cbuf(3 * std::max(p->k_cross, 1), NAN);
     R.cross = cbuf.data();
+    R.n_out = n_out;
+    R.t_out = t_out;
+    R.s_out = n_out > 0 ? s_out + (int64_t)8 * n_out * i : nullptr;
     double cst[4];
     constants(G.a_chart, R.y, R.y + 4, cst);
     if (c0)

@@ -600,3 +600,48 @@ def test_coordinate_time_agrees_with_affine_integration():
     # the escaped photon's k in coordinate time is rescaled to the entry energy
     np.testing.assert_allclose(ot["c1"][0, esc], ot["c0"][0, esc], rtol=1e-13)
     np.testing.assert_allclose(ot["c1"][3, esc], 0.0, atol=1e-8)  # still null
+
+
+# ---------------------------------------------------------------------------
+# Dense output at coordinate times (method (ii) of Sec. 2.2).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("method", [O.DOPRI5, O.DOPRI5_T])
+def test_dense_output_on_a_circular_orbit(method):
+    """States at ten coordinate times of a circular equatorial orbit: each lies
+    on the circle at the azimuth Omega t_j (plus the start's), with the target
+    time itself in x^0; targets beyond the end stay NaN.  The states come from
+    the cubic Hermite interpolant of a step, whose error on a circle is at most
+    (h Omega)^4 / 384 relative: 2.3e-7 at the step cap h = 0.1 r^{3/2}, r = 7."""
+    a, r = 0.5, 7.0
+    init = _circular(a, r)
+    om = cf.omega_kepler(r, a)
+    T = 2 * np.pi / om
+    bound = (0.1 * r ** 1.5 * om) ** 4 / 384
+    t_out = np.linspace(0.0, 1.9 * T, 10)
+    p = O.Params(method=method, rtol=1e-10, atol=1e-10, t_end=1.9 * T - 1.0, r_escape=1e4)
+    out = O.integrate(init, p, t_out=t_out)
+    so = out["s_out"][0]
+    phi0 = np.arctan2(init["s"][2, 0], init["s"][1, 0])
+    for j, tj in enumerate(t_out[:-1]):
+        assert so[j, 0] == tj
+        assert O.radius(a, *so[j, 1:4]) == pytest.approx(r, rel=bound)
+        dphi = np.angle(np.exp(1j * (np.arctan2(so[j, 2], so[j, 1]) - phi0 - om * tj)))
+        assert abs(dphi) < bound + 1e-8, j
+    assert np.all(np.isnan(so[-1]))  # the last target lies past t_end
+
+
+def test_dense_output_agrees_between_variables():
+    """An eccentric, tilted orbit sampled at 25 times by the affine and the
+    coordinate-time integration: the same states to the tolerance."""
+    a = 0.8
+    init = _circular(a, 12.0, vz=0.03)
+    init["s"][5:8] *= 1.05
+    t_out = np.linspace(5.0, 900.0, 25)
+    pa = O.Params(method=O.DOPRI5, rtol=1e-10, atol=1e-10, t_end=1000.0, r_escape=1e4)
+    pt = O.Params(method=O.DOPRI5_T, rtol=1e-10, atol=1e-10, t_end=1000.0, r_escape=1e4)
+    sa = O.integrate(init, pa, t_out=t_out)["s_out"][0]
+    st = O.integrate(init, pt, t_out=t_out)["s_out"][0]
+    assert np.all(np.isfinite(sa)) and np.all(np.isfinite(st))
+    # interpolation error of either side, (h / period)^4-small (see above)
+    np.testing.assert_allclose(st[:, :4], sa[:, :4], rtol=1e-7, atol=5e-7)
+    np.testing.assert_allclose(st[:, 4:], sa[:, 4:], rtol=1e-6, atol=1e-8)
