@@ -102,6 +102,13 @@ typedef struct {
                        it longest-expected-first (see there), the other init calls write the natural order.
                        A caller-written order must be a permutation of the tile numbers; entries out of range
                        are skipped by the integrator (their rays are then not integrated). */
+  int32_t n_out;         /* dense output (method (ii) of Sec. 2.2): number of target coordinate times, 0 = none */
+  const double *t_out;   /* [n_out] ascending coordinate times, device memory, or NULL when n_out == 0 */
+  double *s_out;         /* [n][n_out][8]: (x^mu, k^mu) of each geodesic at t_out[j], taken from the cubic
+                            Hermite interpolant of the step that reaches t_out[j] (DOPRI5 methods); in
+                            coordinate time k^0 is fixed by the entry energy as on exit.  kh_integrate writes
+                            the targets in [t at entry, t at exit] (a target equal to the entry time gets the
+                            entry state) and leaves every other entry untouched. */
 } kh_state;
 
 /* Integration rules.  Defaults (kh_default_params): DOPRI5, FP64,

@@ -46,6 +46,9 @@ struct KState {
   double* c0;
   double* c1;
   int32_t* order;  // tile permutation or nullptr
+  int32_t n_out;   // dense-output targets
+  const double* t_out;
+  double* s_out;
 };
 
 struct KParams {
@@ -75,6 +78,9 @@ inline KState to_k(const kh_state* st) {
   k.c0 = st->c0;
   k.c1 = st->c1;
   k.order = st->order;
+  k.n_out = st->n_out;
+  k.t_out = st->t_out;
+  k.s_out = st->s_out;
   return k;
 }
 

@@ -30,7 +30,7 @@ using namespace khi;
 // The Python binding mirrors these layouts with ctypes.
 static_assert(sizeof(kh_camera) == 64, "kh_camera layout");
 static_assert(sizeof(kh_params) == 112, "kh_params layout");
-static_assert(sizeof(kh_state) == 128, "kh_state layout");
+static_assert(sizeof(kh_state) == 152, "kh_state layout");
 
 namespace {
 
@@ -208,7 +208,9 @@ __device__ inline void flush_crossings(double* q, int* qcnt, int count, const KS
 // FORM: right-hand-side evaluation (KH_RHS_FACTORED / KH_RHS_PAPER).
 // ---------------------------------------------------------------------------
 // WPE: minimum waves per SIMD the register allocation must allow (1 = no limit).
-template <int METHOD, int PREC, int FORM, int WPE>
+// DENSE: dense output compiled in (separate variants, so the interpolation code
+// adds no registers to the ordinary kernels).
+template <int METHOD, int PREC, int FORM, int WPE, bool DENSE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE < 2 ? 2 : WPE)))
 k_integrate(KParams P, KState S, unsigned long long* qctr) {
   using TS = typename std::conditional<PREC == KH_P32, float, double>::type;  // state / stages
@@ -242,6 +244,9 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
   TS r_cur = TS(0), rdot_cur = TS(0);
   TS a_c = TS(0);
   double h = 0.0, lam = 0.0, rcap = 0.0, E0 = 0.0;
+  // dense output: next target index and time (infinite when none is left)
+  int j_out = 0;
+  double t_next = __builtin_inf();
   int kind = 0, nacc = 0, nrej = 0, ncross = 0, status = KH_ACTIVE;
   // Unwrapped azimuth = atan2(y, x) + 2 pi * wind: wind counts passages across
   // the negative x axis, so no arctangent is needed on ordinary steps.
@@ -320,6 +325,26 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
             k[0] = TS(1);
 #pragma unroll
             for (int c = 1; c < 4; ++c) k[c] = (TS)(kd[c] * ik0);
+          }
+          if (DENSE && S.n_out > 0) {
+            // first target at or after the entry time; one equal to it takes the entry state
+            const double te = S.s[id];
+            int lo = 0, hi = S.n_out;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (S.t_out[mid] < te)
+                lo = mid + 1;
+              else
+                hi = mid;
+            }
+            j_out = lo;
+            if (j_out < S.n_out && S.t_out[j_out] == te) {
+              double* o = S.s_out + ((int64_t)id * S.n_out + j_out) * 8;
+#pragma unroll
+              for (int c = 0; c < 8; ++c) o[c] = S.s[c * n + id];
+              ++j_out;
+            }
+            t_next = j_out < S.n_out ? S.t_out[j_out] : __builtin_inf();
           }
           h = S.h[id];
           lam = S.lam[id];
@@ -460,6 +485,32 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
                   }
                   ++ncross;
                 }
+              }
+              // dense output at every target time this step passed (never past t_end)
+              while (DENSE && (double)xn[0] >= t_next && !(P.t_end > 0.0 && t_next > P.t_end)) {
+                double* o = S.s_out + ((int64_t)ray * S.n_out + j_out) * 8;
+                double xo[4], ko[4];
+                const double th = CT ? (t_next - (double)x[0]) / hd
+                                     : hermite_zero((double)x[0] - t_next, (double)k[0], (double)xn[0] - t_next,
+                                                    (double)kn[0], hd);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                  xo[c] = herm(th, (double)x[c], (double)k[c], (double)xn[c], (double)kn[c], hd);
+                  ko[c] = herm(th, (double)k[c], (double)a1[c], (double)kn[c], (double)a7[c], hd);
+                }
+                xo[0] = t_next;
+                double ks = 1.0;
+                if (CT) {  // k^mu = k^0 (1, v) with k^0 from the entry energy, as on exit
+                  ko[0] = 1.0;
+                  ks = E0 / energy((double)a_c, xo, ko);
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                  o[c] = xo[c];
+                  o[4 + c] = ks * ko[c];
+                }
+                ++j_out;
+                t_next = j_out < S.n_out ? S.t_out[j_out] : __builtin_inf();
               }
               if ((double)r_new < rcap)
                 status = KH_CAPTURED;
@@ -907,6 +958,10 @@ kh_status check_state(kh_ctx* ctx, const kh_state* st, bool need_cross) {
     return fail(ctx, KH_EINVAL, "state.n_cross must be NULL or 4-byte aligned device memory");
   if (st->order && (!aligned(st->order, 4) || !device_ok(st->order)))
     return fail(ctx, KH_EINVAL, "state.order must be NULL or 4-byte aligned device memory");
+  if (st->n_out < 0) return fail(ctx, KH_EINVAL, "state.n_out must be >= 0");
+  if (st->n_out > 0 && (!st->t_out || !st->s_out || !aligned(st->t_out, 8) || !aligned(st->s_out, 8) ||
+                        !device_ok(st->t_out) || !device_ok(st->s_out)))
+    return fail(ctx, KH_EINVAL, "state.n_out > 0 needs t_out and s_out in 8-byte aligned device memory");
   if (need_cross && st->k_cross > 0 && (!st->cross || !st->n_cross))
     return fail(ctx, KH_EINVAL, "state.k_cross > 0 requires cross and n_cross");
   return KH_OK;
@@ -923,17 +978,30 @@ using namespace khi;
 
 namespace {
 
-template <int M, int P, int F, int W>
+template <int M, int P, int F, int W, bool D>
 void* kernel_ptr() {
-  return reinterpret_cast<void*>(&k_integrate<M, P, F, W>);
+  return reinterpret_cast<void*>(&k_integrate<M, P, F, W, D>);
 }
 
 // Kernel variants: every method / precision / form at the default register
 // budget, plus DOPRI5 with the factored right-hand side at 2, 3 and 4 waves per
-// SIMD for the occupancy choice.
-void* pick_kernel(int method, int prec, int form, int wpe) {
+// SIMD for the occupancy choice; dense output in variants of its own for the
+// DOPRI5 methods with the factored form at the default budget.
+void* pick_kernel(int method, int prec, int form, int wpe, bool dense) {
+  if (dense) {
+#define KH_PICKD(M, P) \
+  if (method == M && prec == P && form == KH_RHS_FACTORED) return kernel_ptr<M, P, KH_RHS_FACTORED, 1, true>();
+    KH_PICKD(KH_DOPRI5, KH_P64)
+    KH_PICKD(KH_DOPRI5, KH_P32)
+    KH_PICKD(KH_DOPRI5, KH_PMIXED)
+    KH_PICKD(KH_DOPRI5_T, KH_P64)
+    KH_PICKD(KH_DOPRI5_T, KH_P32)
+    KH_PICKD(KH_DOPRI5_T, KH_PMIXED)
+#undef KH_PICKD
+    return nullptr;
+  }
 #define KH_PICK(M, P, F, W) \
-  if (method == M && prec == P && form == F && wpe == W) return kernel_ptr<M, P, F, W>();
+  if (method == M && prec == P && form == F && wpe == W) return kernel_ptr<M, P, F, W, false>();
   KH_PICK(KH_RK4, KH_P64, KH_RHS_FACTORED, 1)
   KH_PICK(KH_RK4, KH_P32, KH_RHS_FACTORED, 1)
   KH_PICK(KH_RK4, KH_PMIXED, KH_RHS_FACTORED, 1)
@@ -1195,8 +1263,8 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   if (p->method != KH_RK4 && (!(p->rtol > 0.0) || !(p->atol > 0.0) || !(p->hmax_coeff > 0.0)))
     return fail(ctx, KH_EINVAL, "DOPRI5 needs rtol, atol, hmax_coeff > 0");
   if (p->k_cross < 0 || p->k_cross > 8) return fail(ctx, KH_EINVAL, "k_cross must be in [0, 8]");
-  if (p->method == KH_RK4 && (p->k_cross > 0 || p->t_end > 0.0))
-    return fail(ctx, KH_EUNSUPPORTED, "crossings and t_end need the DOPRI5 dense output");
+  if (p->method == KH_RK4 && (p->k_cross > 0 || p->t_end > 0.0 || (st && st->n_out > 0)))
+    return fail(ctx, KH_EUNSUPPORTED, "crossings, t_end and dense output need a DOPRI5 method");
   if (p->k_cross > 0 && p->t_end > 0.0)
     return fail(ctx, KH_EUNSUPPORTED, "crossing records and t_end landing are not combined");
   if (p->rhs_form == KH_RHS_PAPER && p->precision == KH_PMIXED)
@@ -1237,7 +1305,7 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   // (spilling a few registers) than at two; FP64 and FP32 do not gain.
   int wpe = p->waves_per_eu;
   if (wpe == 0) wpe = (p->method != KH_RK4 && p->precision == KH_PMIXED && p->rhs_form == KH_RHS_FACTORED) ? 3 : 1;
-  void* fn = pick_kernel(p->method, p->precision, p->rhs_form, wpe);
+  void* fn = pick_kernel(p->method, p->precision, p->rhs_form, wpe, st->n_out > 0);
   if (!fn) return fail(ctx, KH_EUNSUPPORTED, "no kernel for this method / precision / rhs_form / waves_per_eu");
   // dynamic LDS: one crossing queue (kQFields x kQCap doubles + a counter) per wave
   const size_t lds = p->k_cross > 0 ? (size_t)(block / 64) * (kQFields * kQCap + 1) * sizeof(double) : 0;

@@ -434,3 +434,49 @@ def test_coordinate_time_particles_parity(ctx):
     assert np.median(da) < 1e-5 and np.quantile(da, 0.9) < 1e-4
     e = np.abs(g["c1"][0] - g["c0"][0]) / np.abs(g["c0"][0])
     assert np.max(e[landed]) < 1e-12
+
+
+@pytest.mark.parametrize("method", [K.DOPRI5, K.DOPRI5_T])
+def test_dense_output_parity(ctx, method):
+    """Dense output at 40 coordinate times (method (ii) of Sec. 2.2) for a
+    sample of the particle workload and for the rays of a small image, in the
+    affine parameter and in coordinate time, against the oracle's dense
+    output element by element; targets a ray does not reach stay NaN."""
+    say(f"dense output method={method}")
+    t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()  # noqa: E731
+    # particles
+    pw = W.particles()
+    idx = np.arange(0, 1 << 20, 8191)[:128]
+    a, x3, v3 = pw["a"][idx], pw["x3"][:, idx].copy(), pw["v3"][:, idx].copy()
+    t_out = np.concatenate([[0.0], np.sort(np.random.default_rng(5).uniform(1.0, 3000.0, 38)), [3000.0]])
+    st = K.State(len(idx), t_out=t_out)
+    ctx.kh_init_geodesics(K.TIMELIKE, t(a), t(x3), t(v3), st)
+    p = K.kh_default_params(method=method, t_end=3000.0, r_escape=1e4)
+    ctx.kh_integrate(p, st)
+    g = st.numpy()
+    o = O.integrate(O.timelike(a, x3, v3), oracle_params(p), t_out=t_out)
+    assert np.array_equal(g["status"], o["status"])
+    assert np.array_equal(np.isnan(g["s_out"]), np.isnan(o["s_out"]))
+    fin = ~np.isnan(o["s_out"])
+    assert fin[:, :, 0].sum() >= 0.9 * fin[:, :, 0].size
+    assert np.all(g["s_out"][:, :, 0][fin[:, :, 0]] == np.broadcast_to(t_out, fin.shape[:2])[fin[:, :, 0]])
+    d = np.abs(g["s_out"] - o["s_out"])[fin] / np.maximum(np.abs(o["s_out"][fin]), 1.0)
+    say(f"  particles: max rel {d.max():.2e}")
+    assert d.max() < 1e-6
+    # image rays (null): targets along the way in
+    cam = W.Camera(0.9, 1000.0, 40.0, -8, 8, -8, 8, 23, 19)
+    t_img = np.linspace(0.0, 1900.0, 20)
+    st = K.State(cam.n, t_out=t_img)
+    ctx.kh_init_rays([kcam(cam)], st)
+    pi = K.kh_default_params(method=method)
+    ctx.kh_integrate(pi, st)
+    g = st.numpy()
+    init = O.camera_rays(cam.a, cam.r_obs, cam.incl, cam.alpha_min, cam.alpha_max, cam.beta_min, cam.beta_max,
+                         cam.width, cam.height)
+    oo = O.integrate(init, oracle_params(pi), t_out=t_img)
+    assert np.array_equal(g["status"], oo["status"])
+    assert np.array_equal(np.isnan(g["s_out"]), np.isnan(oo["s_out"]))
+    fin = ~np.isnan(oo["s_out"])
+    d = np.abs(g["s_out"] - oo["s_out"])[fin] / np.maximum(np.abs(oo["s_out"][fin]), 1.0)
+    say(f"  image: max rel {d.max():.2e}, targets reached {fin[:, :, 0].mean():.2f}")
+    assert d.max() < 1e-6
