@@ -46,9 +46,9 @@ def kernel_source_hash():
 # (FETCH_SIZE, WRITE_SIZE, calibrated against a plain copy) and hardware FP64
 # FLOP per launch (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes), valid only for the
 # kernel source they were taken on.
-PROFILED = {"source_hash": "3939c77042a60ccc",
-            "traffic_bytes": (120206.5625 * 2.0 + 309798.4375 * 1.0) * 1024,
-            "hw_fp64_flops": 6337090547.0 * 64}
+PROFILED = {"source_hash": "4f1f01cd2ecfc905",
+            "traffic_bytes": (120267.0625 * 2.0 + 309066.59375 * 1.0) * 1024,
+            "hw_fp64_flops": 6335145857.0 * 64}
 
 
 def algorithmic_flops(K, stats, n_rays, method, form):
@@ -307,6 +307,22 @@ def particles_extra(ctx, K, W, torch):
     both = l64 & l32
     d = np.linalg.norm(s32[1:4, both] - s64[1:4, both], axis=0) / np.linalg.norm(s64[1:4, both], axis=0)
     out["fp32_vs_fp64_position"] = dict(median=float(np.median(d)), p99=float(np.quantile(d, 0.99)))
+    # dense output: the FP64 coordinate-time run again with states at 100 times
+    t_out = np.linspace(100.0, 1e4, 100)
+    st = K.State(n, t_out=t_out)
+    p = K.kh_default_params(method=K.DOPRI5_T, t_end=1e4, r_escape=1e4)
+    ctx.kh_init_geodesics(K.TIMELIKE, spin, x3, v3, st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.kh_integrate(p, st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    reached = float(torch.isfinite(st.s_out[:, :, 0]).float().mean().item())
+    out["fp64_coordinate_time_dense_100"] = dict(seconds=dt, particles_per_s=n / dt, targets=100,
+                                                 fraction_reached=reached,
+                                                 output_bytes=int(st.s_out.numel() * 8))
+    log(f"particles fp64 coordinate time + 100 dense outputs: {dt:.3f} s ({reached:.3f} of targets reached)")
+    del st
     (sct, lct) = finals["fp64_coordinate_time"]
     both = l64 & lct
     d = np.linalg.norm(sct[1:4, both] - s64[1:4, both], axis=0) / np.linalg.norm(s64[1:4, both], axis=0)
