@@ -7,7 +7,9 @@ never imports, links or calls it, and it shares no source with the GPU path.
 The numerics live in ``kerr_oracle.cpp`` (plain Christoffel form of the geodesic
 equation, eq:geo of Sec. 2.1, on the metric def:CKS with dual-number
 derivatives and a generic 4x4 inverse; classic RK4 of Sec. 3 and a
-Dormand-Prince 5(4) pair).  This module is argument marshalling over ctypes.
+Dormand-Prince 5(4) pair; the same Christoffel form on the Boyer-Lindquist
+line element of Sec. 2.1 for the chart comparison of Sec. 4).  This module is
+argument marshalling over ctypes.
 
 Array layouts follow the GPU library's: states are ``[8][n]`` (x^0..x^3,
 k^0..k^3), constants ``[4][n]`` = (E, L_z, Q, mu^2), crossings ``[n][K][3]`` =
@@ -105,6 +107,13 @@ def lib():
         L.oracle_redshift.argtypes = [d, d, d]
         L.oracle_redshift.restype = d
         L.oracle_dopri5_sho.argtypes = [pd, d, i64, d, pd]
+        L.oracle_bl_metric.argtypes = [d, pd, pd, pd]
+        L.oracle_bl_rhs.argtypes = [d, pd, pd, pd]
+        L.oracle_bl_constants.argtypes = [d, pd, pd, pd]
+        L.oracle_bl_to_ks.argtypes = [d, pd, pd, pd]
+        L.oracle_ks_to_bl.argtypes = [d, i64, pd, pd]
+        L.oracle_ks_to_bl.restype = i64
+        L.oracle_rk4_fixed.argtypes = [i32, d, d, d, d, i32, i64, pd, pi32, pi32, i32]
         _lib = L
     return _lib
 
@@ -240,3 +249,64 @@ def dopri5_sho(y0, h, nsteps, rtol=1e-8):
     out = np.zeros(9)
     lib().oracle_dopri5_sho(_p(y0, C.c_double), h, nsteps, rtol, _p(out, C.c_double))
     return out[:8], out[8]
+
+
+# ---------------------------------------------------------------------------
+# Boyer-Lindquist chart and fixed-step RK4 in either chart (Sec. 4, tab:elapse).
+# BL states are (t, r, theta, phi, k^t, k^r, k^theta, k^phi).
+# ---------------------------------------------------------------------------
+CHARTS = {"ks": 0, "bl": 1}
+
+
+def bl_metric(a, x):
+    x = _f64(x)
+    g = np.zeros(16)
+    dg = np.zeros(64)
+    lib().oracle_bl_metric(a, _p(x, C.c_double), _p(g, C.c_double), _p(dg, C.c_double))
+    return g.reshape(4, 4), dg.reshape(4, 4, 4)
+
+
+def bl_rhs(a, x, k):
+    x, k = _f64(x), _f64(k)
+    acc = np.zeros(4)
+    lib().oracle_bl_rhs(a, _p(x, C.c_double), _p(k, C.c_double), _p(acc, C.c_double))
+    return acc
+
+
+def bl_constants(a, x, k):
+    """(E, L_z, Q, mu^2) of a Boyer-Lindquist state."""
+    x, k = _f64(x), _f64(k)
+    out = np.zeros(4)
+    lib().oracle_bl_constants(a, _p(x, C.c_double), _p(k, C.c_double), _p(out, C.c_double))
+    return out
+
+
+def bl_to_ks(a, xbl):
+    """Kerr-Schild point and Jacobian d x_KS / d x_BL of a Boyer-Lindquist point."""
+    xbl = _f64(xbl)
+    xks = np.zeros(4)
+    J = np.zeros(16)
+    lib().oracle_bl_to_ks(a, _p(xbl, C.c_double), _p(xks, C.c_double), _p(J, C.c_double))
+    return xks, J.reshape(4, 4)
+
+
+def ks_to_bl(a, s_ks):
+    """Boyer-Lindquist states [8][n] of Kerr-Schild states [8][n] (chart spin a)."""
+    y = np.ascontiguousarray(np.asarray(s_ks, dtype=np.float64).T)
+    out = np.zeros_like(y)
+    lib().oracle_ks_to_bl(a, y.shape[0], _p(y, C.c_double), _p(out, C.c_double))
+    return np.ascontiguousarray(out.T)
+
+
+def rk4_fixed(chart, a, h_coeff, r_stop, r_escape, nsteps, s, status=None, steps=None, nthreads=0):
+    """Up to ``nsteps`` RK4 steps of h = h_coeff * r per active geodesic.
+
+    ``chart`` is "ks" or "bl"; ``s`` is [8][n] in that chart.  Returns
+    (s, status, steps) as new arrays; ``steps`` accumulates the steps taken."""
+    y = np.ascontiguousarray(np.asarray(s, dtype=np.float64).T).copy()
+    n = y.shape[0]
+    st = np.zeros(n, np.int32) if status is None else np.array(status, dtype=np.int32)
+    sp = np.zeros(n, np.int32) if steps is None else np.array(steps, dtype=np.int32)
+    lib().oracle_rk4_fixed(CHARTS[chart], a, h_coeff, r_stop, r_escape, nsteps, n, _p(y, C.c_double),
+                           _p(st, C.c_int32), _p(sp, C.c_int32), nthreads)
+    return np.ascontiguousarray(y.T), st, sp

@@ -19,7 +19,11 @@
 //   * classic fourth-order Runge-Kutta (Sec. 3, the default integrator) and
 //     the Dormand-Prince 5(4) embedded pair with the step controller, the
 //     termination rules, equatorial-crossing records, redshift and constants
-//     of motion that the GPU library documents in include/kerrhip.h.
+//     of motion that the GPU library documents in include/kerrhip.h;
+//   * for the chart comparison of Sec. 4 (tab:elapse): the Boyer-Lindquist
+//     line element of Sec. 2.1 through the same dual-number / Gauss-Jordan /
+//     Christoffel route, the map from ingoing Kerr-Schild to Boyer-Lindquist
+//     states, and fixed-step RK4 in either chart.
 //
 // Everything is double precision.  Parallelism is a std::thread pool over
 // chunks of 64 geodesics; geodesics are independent, so results do not depend
@@ -83,6 +87,28 @@ inline Dual sqrt(const Dual& a) {
   for (int i = 0; i < 3; ++i) r.d[i] = a.d[i] / (2.0 * s);
   return r;
 }
+inline Dual sin(const Dual& a) {
+  Dual r{std::sin(a.v), {0.0, 0.0, 0.0}};
+  double c = std::cos(a.v);
+  for (int i = 0; i < 3; ++i) r.d[i] = a.d[i] * c;
+  return r;
+}
+inline Dual cos(const Dual& a) {
+  Dual r{std::cos(a.v), {0.0, 0.0, 0.0}};
+  double sn = std::sin(a.v);
+  for (int i = 0; i < 3; ++i) r.d[i] = -a.d[i] * sn;
+  return r;
+}
+inline Dual log(const Dual& a) {
+  Dual r{std::log(a.v), {0.0, 0.0, 0.0}};
+  for (int i = 0; i < 3; ++i) r.d[i] = a.d[i] / a.v;
+  return r;
+}
+inline Dual fabs(const Dual& a) { return a.v < 0.0 ? 0.0 - a : a; }
+using std::cos;
+using std::fabs;
+using std::log;
+using std::sin;
 using std::sqrt;
 
 const double ETA[4] = {-1.0, 1.0, 1.0, 1.0};
@@ -168,11 +194,11 @@ bool invert4(const double A[4][4], double Ainv[4][4]) {
   return true;
 }
 
-// The geodesic equation with Christoffel symbols (eq:geo):
+// The geodesic equation with Christoffel symbols (eq:geo), for any chart given
+// its metric g and derivatives dg[c][m][n] = d g_{mn} / d x^c at the point:
 //   acc^mu = -Gamma^mu_{ab} k^a k^b.
-void geodesic_rhs(double a, const double x[4], const double k[4], double acc[4]) {
-  double g[4][4], dg[4][4][4], gi[4][4];
-  metric_and_derivs(a, x, g, dg);
+void christoffel_acc(const double g[4][4], const double dg[4][4][4], const double k[4], double acc[4]) {
+  double gi[4][4];
   if (!invert4(g, gi)) {
     for (int m = 0; m < 4; ++m) acc[m] = NAN;
     return;
@@ -192,6 +218,13 @@ void geodesic_rhs(double a, const double x[4], const double k[4], double acc[4])
       }
     acc[m] = -s;
   }
+}
+
+// Kerr-Schild right-hand side.
+void geodesic_rhs(double a, const double x[4], const double k[4], double acc[4]) {
+  double g[4][4], dg[4][4][4];
+  metric_and_derivs(a, x, g, dg);
+  christoffel_acc(g, dg, k, acc);
 }
 
 // First-order form of the system: y = (x^mu, k^mu), y' = (k^mu, acc^mu).
@@ -1055,6 +1088,242 @@ void oracle_dopri5_sho(const double y0[8], double h, int64_t nsteps, double rtol
   }
   std::memcpy(out, y, sizeof y);
   out[8] = err;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Boyer-Lindquist chart (the line element at the start of Sec. 2.1) and
+// fixed-step RK4 in either chart: the workload of the benchmark of Sec. 4
+// (tab:elapse), which integrates the same rays in both charts.
+// ============================================================================
+namespace {
+
+enum { CHART_KS = 0, CHART_BL = 1 };
+
+// Boyer-Lindquist metric in coordinates (t, r, theta, phi), M = 1, with
+// rho^2 = r^2 + a^2 cos^2(theta) and Delta = r^2 - 2 r + a^2:
+//   g_tt = -(1 - 2 r / rho^2),  g_t phi = -2 a r sin^2(theta) / rho^2,
+//   g_rr = rho^2 / Delta,       g_theta theta = rho^2,
+//   g_phi phi = (r^2 + a^2 + 2 a^2 r sin^2(theta) / rho^2) sin^2(theta).
+template <class S>
+void bl_metric(double a, const S& r, const S& th, S g[4][4]) {
+  S s = sin(th), c = cos(th);
+  S rho2 = r * r + a * a * c * c;
+  S Delta = r * r - 2.0 * r + a * a;
+  S zero = 0.0 * r;
+  for (int m = 0; m < 4; ++m)
+    for (int n = 0; n < 4; ++n) g[m][n] = zero;
+  g[0][0] = 2.0 * r / rho2 - 1.0;
+  g[0][3] = (-2.0 * a) * r * s * s / rho2;
+  g[3][0] = g[0][3];
+  g[1][1] = rho2 / Delta;
+  g[2][2] = rho2;
+  g[3][3] = (r * r + a * a + 2.0 * a * a * r * s * s / rho2) * s * s;
+}
+
+// Metric and derivatives dg[c][m][n] = d g_{mn} / d x^c by dual numbers in
+// (r, theta); the metric depends on neither t nor phi.
+void bl_metric_and_derivs(double a, const double x[4], double g[4][4], double dg[4][4][4]) {
+  Dual R = seed(x[1], 0), TH = seed(x[2], 1);
+  Dual gd[4][4];
+  bl_metric(a, R, TH, gd);
+  for (int m = 0; m < 4; ++m)
+    for (int n = 0; n < 4; ++n) {
+      g[m][n] = gd[m][n].v;
+      dg[0][m][n] = 0.0;
+      dg[1][m][n] = gd[m][n].d[0];
+      dg[2][m][n] = gd[m][n].d[1];
+      dg[3][m][n] = 0.0;
+    }
+}
+
+void bl_rhs(double a, const double x[4], const double k[4], double acc[4]) {
+  double g[4][4], dg[4][4][4];
+  bl_metric_and_derivs(a, x, g, dg);
+  christoffel_acc(g, dg, k, acc);
+}
+
+void deriv_bl(double a, const double y[8], double dy[8]) {
+  for (int m = 0; m < 4; ++m) dy[m] = y[4 + m];
+  bl_rhs(a, y, y + 4, dy + 4);
+}
+
+// E = -k_t, L_z = k_phi, mu^2 = -g k k and Carter's constant
+// Q = k_theta^2 + cos^2(theta) [a^2 (mu^2 - E^2) + L_z^2 / sin^2(theta)].
+void bl_constants(double a, const double x[4], const double k[4], double out[4]) {
+  double g[4][4];
+  bl_metric(a, x[1], x[2], g);
+  double kl[4], mu2 = 0.0;
+  for (int m = 0; m < 4; ++m) {
+    kl[m] = 0.0;
+    for (int n = 0; n < 4; ++n) kl[m] += g[m][n] * k[n];
+    mu2 -= kl[m] * k[m];
+  }
+  double E = -kl[0], Lz = kl[3];
+  double c = std::cos(x[2]), s = std::sin(x[2]);
+  out[0] = E;
+  out[1] = Lz;
+  out[2] = kl[2] * kl[2] + c * c * (a * a * (mu2 - E * E) + Lz * Lz / (s * s));
+  out[3] = mu2;
+}
+
+// Ingoing Kerr-Schild coordinates from Boyer-Lindquist ones (|a| < 1): with
+// r_pm = 1 +- sqrt(1 - a^2), the time and azimuth shifts
+//   F(r) = int 2 r / Delta dr = 2 (r_+ ln|r - r_+| - r_- ln|r - r_-|) / (r_+ - r_-),
+//   G(r) = int a / Delta dr   = a ln|(r - r_+) / (r - r_-)| / (r_+ - r_-),
+// give T = t + F(r), psi = phi + G(r) and the Cartesian form
+//   x + i y = (r + i a) sin(theta) e^{i psi},  z = r cos(theta),
+// which satisfies eq:CKSr and carries the metric def:CKS (pinned by pulling
+// def:CKS back through this map).
+template <class S>
+S shift_F(double a, const S& r) {
+  double rp = 1.0 + std::sqrt(1.0 - a * a), rm = 1.0 - std::sqrt(1.0 - a * a);
+  return (2.0 / (rp - rm)) * (rp * log(fabs(r - rp)) - rm * log(fabs(r - rm)));
+}
+template <class S>
+S shift_G(double a, const S& r) {
+  double rp = 1.0 + std::sqrt(1.0 - a * a), rm = 1.0 - std::sqrt(1.0 - a * a);
+  return (a / (rp - rm)) * log(fabs((r - rp) / (r - rm)));
+}
+template <class S>
+void bl_to_ks(double a, const S& r, const S& th, const S& ph, S& F, S& X, S& Y, S& Z) {
+  F = shift_F(a, r);
+  S psi = ph + shift_G(a, r);
+  S sn = sin(th);
+  X = sn * (r * cos(psi) - a * sin(psi));
+  Y = sn * (r * sin(psi) + a * cos(psi));
+  Z = r * cos(th);
+}
+
+// Kerr-Schild point xks and Jacobian J[mu][nu] = d x_KS^mu / d x_BL^nu at the
+// Boyer-Lindquist point xbl.
+void bl_to_ks_jacobian(double a, const double xbl[4], double xks[4], double J[4][4]) {
+  Dual R = seed(xbl[1], 0), TH = seed(xbl[2], 1), PH = seed(xbl[3], 2);
+  Dual F, X, Y, Z;
+  bl_to_ks(a, R, TH, PH, F, X, Y, Z);
+  xks[0] = xbl[0] + F.v;
+  xks[1] = X.v;
+  xks[2] = Y.v;
+  xks[3] = Z.v;
+  const Dual* row[4] = {&F, &X, &Y, &Z};
+  for (int m = 0; m < 4; ++m) {
+    J[m][0] = (m == 0) ? 1.0 : 0.0;
+    for (int j = 0; j < 3; ++j) J[m][j + 1] = row[m]->d[j];
+  }
+}
+
+// Kerr-Schild state -> Boyer-Lindquist state: r from eq:CKSr,
+// cos(theta) = z / r, psi = atan2(y, x) - atan2(a, r), phi = psi - G(r),
+// t = T - F(r); the momentum is J^{-1} k with J of the map above.
+bool ks_to_bl_state(double a, const double yk[8], double yb[8]) {
+  double r = ks_radius(a, yk[1], yk[2], yk[3]);
+  double ct = std::max(-1.0, std::min(1.0, yk[3] / r));
+  double th = std::acos(ct);
+  double ph = std::atan2(yk[2], yk[1]) - std::atan2(a, r) - shift_G(a, r);
+  yb[0] = yk[0] - shift_F(a, r);
+  yb[1] = r;
+  yb[2] = th;
+  yb[3] = ph;
+  double xks[4], J[4][4], Ji[4][4];
+  bl_to_ks_jacobian(a, yb, xks, J);
+  if (!invert4(J, Ji)) return false;
+  for (int m = 0; m < 4; ++m) {
+    yb[4 + m] = 0.0;
+    for (int n = 0; n < 4; ++n) yb[4 + m] += Ji[m][n] * yk[4 + n];
+  }
+  return true;
+}
+
+double chart_radius(int chart, double a, const double y[8]) { return chart == CHART_BL ? y[1] : radius(a, y); }
+double chart_rdot(int chart, double a, const double y[8]) { return chart == CHART_BL ? y[5] : rdot(a, y); }
+
+// Up to nsteps classic RK4 steps of h = h_coeff * r (r at the step's start),
+// no error control.  After each step: a NaN component ends the geodesic as
+// failed, r < r_stop as captured, r > r_escape with dr/dlambda > 0 as escaped.
+// Only active geodesics are stepped; `steps` counts the steps taken.
+void rk4_fixed(int chart, double a, double hc, double r_stop, double r_esc, int32_t nsteps, double y[8],
+               int32_t& st, int32_t& steps) {
+  if (st != ST_ACTIVE) return;
+  auto F = [&](const double* yy, double* dy) {
+    if (chart == CHART_BL)
+      deriv_bl(a, yy, dy);
+    else
+      deriv(a, yy, dy);
+  };
+  for (int32_t s = 0; s < nsteps; ++s) {
+    double h = hc * chart_radius(chart, a, y);
+    double k1[8], k2[8], k3[8], k4[8], t[8];
+    F(y, k1);
+    for (int c = 0; c < 8; ++c) t[c] = y[c] + 0.5 * h * k1[c];
+    F(t, k2);
+    for (int c = 0; c < 8; ++c) t[c] = y[c] + 0.5 * h * k2[c];
+    F(t, k3);
+    for (int c = 0; c < 8; ++c) t[c] = y[c] + h * k3[c];
+    F(t, k4);
+    for (int c = 0; c < 8; ++c) y[c] += h / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+    ++steps;
+    if (any_nan(y)) {
+      st = ST_FAILED;
+      return;
+    }
+    double r = chart_radius(chart, a, y);
+    if (r < r_stop) {
+      st = ST_CAPTURED;
+      return;
+    }
+    if (r > r_esc && chart_rdot(chart, a, y) > 0.0) {
+      st = ST_ESCAPED;
+      return;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void oracle_bl_metric(double a, const double x[4], double g[16], double dg[64]) {
+  double gg[4][4], d[4][4][4];
+  bl_metric_and_derivs(a, x, gg, d);
+  for (int m = 0; m < 4; ++m)
+    for (int q = 0; q < 4; ++q) {
+      g[4 * m + q] = gg[m][q];
+      for (int c = 0; c < 4; ++c) dg[16 * c + 4 * m + q] = d[c][m][q];
+    }
+}
+
+void oracle_bl_rhs(double a, const double x[4], const double k[4], double acc[4]) { bl_rhs(a, x, k, acc); }
+
+void oracle_bl_constants(double a, const double x[4], const double k[4], double out[4]) {
+  bl_constants(a, x, k, out);
+}
+
+void oracle_bl_to_ks(double a, const double xbl[4], double xks[4], double jac[16]) {
+  double J[4][4];
+  bl_to_ks_jacobian(a, xbl, xks, J);
+  for (int m = 0; m < 4; ++m)
+    for (int n = 0; n < 4; ++n) jac[4 * m + n] = J[m][n];
+}
+
+// y_ks, y_bl: [n][8].  Returns the number of states whose Jacobian was singular
+// (their output is NaN).
+int64_t oracle_ks_to_bl(double a, int64_t n, const double* y_ks, double* y_bl) {
+  int64_t bad = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (!ks_to_bl_state(a, y_ks + 8 * i, y_bl + 8 * i)) {
+      for (int c = 0; c < 8; ++c) y_bl[8 * i + c] = NAN;
+      ++bad;
+    }
+  return bad;
+}
+
+// chart 0 = Kerr-Schild (Cartesian), 1 = Boyer-Lindquist; y [n][8] in place.
+void oracle_rk4_fixed(int32_t chart, double a, double h_coeff, double r_stop, double r_escape, int32_t nsteps,
+                      int64_t n, double* y, int32_t* status, int32_t* steps, int32_t nthreads) {
+  parallel_chunks(n, nthreads, [&](int64_t i) {
+    rk4_fixed(chart, a, h_coeff, r_stop, r_escape, nsteps, y + 8 * i, status[i], steps[i]);
+  });
 }
 
 }  // extern "C"
