@@ -29,15 +29,19 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# The sources the integrator kernel is compiled from (its translation unit and
+# the headers it includes).
+INTEGRATOR_SOURCES = ("kerrhip.hip", "internal.hpp", "ks_math.hpp", "bl_math.hpp", "steppers.hpp")
+
+
 def kernel_source_hash():
     import hashlib
 
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1706_07062_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in INTEGRATOR_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -46,7 +50,7 @@ def kernel_source_hash():
 # (FETCH_SIZE, WRITE_SIZE, calibrated against a plain copy) and hardware FP64
 # FLOP per launch (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes), valid only for the
 # kernel source they were taken on.
-PROFILED = {"source_hash": "4f1f01cd2ecfc905",
+PROFILED = {"source_hash": "28d09e5fd29b6878",
             "traffic_bytes": (120267.0625 * 2.0 + 309066.59375 * 1.0) * 1024,
             "hw_fp64_flops": 6335145857.0 * 64}
 
@@ -194,10 +198,67 @@ def extras(args, ctx, K, W, torch):  # noqa: C901
         res[name] = dict(ns_per_step_per_ray=dt * 1e9 / s["n_acc"], steps=s["n_acc"], kernel_ms=dt * 1e3,
                          workload="a=0.999, 1024x1024, r_obs=1024, 60 deg, h=0.01r")
         log(f"{name}: {res[name]['ns_per_step_per_ray']:.4f} ns per RK4 step per ray")
+    res["elapse_table"] = elapse_extra(ctx, K, W, torch)
     res["batched_256_images"] = batched_extra(ctx, K, W, torch)
     res["particles_2p20"] = particles_extra(ctx, K, W, torch)
     res["surrogate_4096"] = surrogate_extra(ctx, K, W, torch, args)
     return res
+
+
+# Sec. 4, tab:elapse, last column (nVidia Titan Black), ns per RK4 step per ray.
+PAPER_TITAN_BLACK_NS = {"fp32_bl_aos": 0.167, "fp32_bl_soa": 0.175, "fp32_ks_aos": 0.297, "fp32_ks_soa": 0.309,
+                        "fp64_bl_aos": 1.65, "fp64_bl_soa": 1.66, "fp64_ks_aos": 1.15, "fp64_ks_soa": 1.15}
+
+
+def elapse_extra(ctx, K, W, torch, reps=5):
+    """The chart / data-layout comparison of Sec. 4 (tab:elapse) on one MI355X:
+    the 1024x1024 image at r = 1024 toward a = 0.999, one launch of 1024
+    fixed RK4 steps (h = r / 256) per ray, in Kerr-Schild and Boyer-Lindquist
+    coordinates, array-of-structures and structure-of-arrays, FP32 and FP64.
+    ns per step per ray = shortest of `reps` launches / (1024 x rays), as in
+    the paper; every ray stays active for the whole launch (checked)."""
+    cam = W.elapse_image(1024)
+    kc = [K.kh_camera(cam.a, cam.r_obs, cam.incl, cam.alpha_min, cam.alpha_max, cam.beta_min, cam.beta_max,
+                      cam.width, cam.height)]
+    st = K.State(cam.n, constants=False, schedule=False)
+    ctx.kh_init_rays(kc, st)
+    r_stop = 1.01 * (1 + (1 - cam.a ** 2) ** 0.5)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    for prec, pname, peak in ((K.P32, "fp32", FP64_PEAK_TFLOPS), (K.P64, "fp64", FP64_PEAK_TFLOPS)):
+        for form, chart in ((K.RHS_BL, "bl"), (K.RHS_FACTORED, "ks")):
+            f = K.kh_flops(K.RK4, form)
+            flop_step = 4 * (f["add"] + f["mul"]) + f["step_add"] + f["step_mul"]
+            for layout, lname in ((K.AOS, "aos"), (K.SOA, "soa")):
+                params = K.fixed_params(form, layout, prec, W.ELAPSE_STEPS, -cam.a, W.ELAPSE_H_COEFF, r_stop,
+                                        cam.r_obs)
+                fs = K.FixedState(ctx, params, st.s)
+                y0 = fs.y.clone()
+                times = []
+                for _ in range(reps):
+                    fs.y.copy_(y0)
+                    fs.status.zero_()
+                    fs.steps.zero_()
+                    e0.record()
+                    ctx.kh_rk4_fixed(params, fs.y, fs.status, fs.steps)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    times.append(e0.elapsed_time(e1))
+                taken = int(fs.steps.sum().item())
+                if taken != W.ELAPSE_STEPS * cam.n:
+                    raise RuntimeError(f"elapse {pname}/{chart}/{lname}: {taken} steps, not 1024 per ray")
+                ms = min(times)
+                tflops = flop_step * taken / (ms * 1e-3) / 1e12
+                key = f"{pname}_{chart}_{lname}"
+                out[key] = dict(ns_per_step_per_ray=ms * 1e6 / taken, launch_ms=ms, alg_tflops=tflops,
+                                alg_frac_fp_vector_peak=tflops / peak, flop_per_step=flop_step,
+                                paper_titan_black_ns=PAPER_TITAN_BLACK_NS[key])
+                log(f"elapse {key}: {ms * 1e6 / taken:.4f} ns per RK4 step per ray ({tflops:.1f} TFLOP/s)")
+                del fs, y0
+    out["workload"] = ("a=0.999, 1024x1024 image at r=1024 M, 60 deg, [-12,12]^2; one launch of 1024 RK4 steps "
+                       "(h = r/256) per ray; shortest of 5 launches")
+    out["peak_note"] = "FP32 and FP64 vector peaks are both 78.6 TFLOP/s without packed FP32 (not used here)"
+    return out
 
 
 def surrogate_extra(ctx, K, W, torch, args):
@@ -404,6 +465,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, help="MiB; plain copy before the run (counter reference)")
     ap.add_argument("--surrogate-rays", type=int, default=10_000_000)
     ap.add_argument("--surrogate-steps", type=int, default=8000)
+    ap.add_argument("--elapse-only", action="store_true",
+                    help="only the fixed-step chart / layout comparison (Sec. 4's tab:elapse), for profilers")
     ap.add_argument("--surrogate-image-only", action="store_true",
                     help="only the network's 4096^2 image, three times, with untrained seed-0 weights (for profilers)")
     args = ap.parse_args()
@@ -415,6 +478,17 @@ def main():
         copy_probe(args.copy_probe)
     if args.surrogate_image_only:
         surrogate_image_only()
+        return
+    if args.elapse_only:
+        import torch
+
+        import paper_1706_07062_amd as K
+        from paper_1706_07062_amd import workloads as W
+
+        torch.cuda.set_device(0)
+        ctx = K.Context(0)
+        print(json.dumps({"elapse_table": elapse_extra(ctx, K, W, torch, reps=max(1, args.steps))}), flush=True)
+        ctx.close()
         return
     out, _ = run_gpu(args)
     if not args.no_cpu:

@@ -61,6 +61,8 @@ enum { KH_NULL = 0, KH_TIMELIKE = 1 };
 enum { KH_RK4 = 0, KH_DOPRI5 = 1, KH_DOPRI5_T = 2 }; /* kh_params.method */
 enum { KH_P64 = 0, KH_P32 = 1, KH_PMIXED = 2 };  /* kh_params.precision */
 enum { KH_RHS_FACTORED = 0, KH_RHS_PAPER = 1 };  /* kh_params.rhs_form */
+enum { KH_RHS_BL = 2 };  /* Boyer-Lindquist chart: kh_rk4_fixed, kh_pack_fixed and kh_flops only */
+enum { KH_SOA = 0, KH_AOS = 1 };                 /* kh_fixed_params.layout */
 
 typedef struct kh_ctx kh_ctx;
 
@@ -162,6 +164,7 @@ typedef struct {
   int64_t add, mul, div, sqrt; /* per right-hand-side evaluation */
   int64_t step_add, step_mul;  /* per DOPRI5 attempt (or RK4 step) outside the RHS */
   int64_t step_div, step_sqrt;
+  int64_t trig;                /* sin and cos evaluations per RHS (Boyer-Lindquist form only) */
 } kh_flop_counts;
 
 /* Create a context on `device` (HIP ordinal).  *out receives the handle. */
@@ -235,8 +238,55 @@ kh_status kh_stats_device(kh_ctx *ctx, const kh_state *st, int64_t *d_out, void 
 kh_status kh_rhs(kh_ctx *ctx, int32_t precision, int32_t rhs_form, const double *spin_chart, const double *s,
                  double *acc, int64_t n, void *stream);
 
-/* Operation counts of the right-hand side and of one step (host only). */
+/* Operation counts of the right-hand side and of one step (host only).
+ * rhs_form KH_RHS_BL is accepted with method KH_RK4. */
 kh_status kh_flops(int32_t method, int32_t rhs_form, kh_flop_counts *out);
+
+/* ---------------------------------------------------------------------------
+ * Fixed-step RK4 in either chart: the workload of the comparison of Sec. 4
+ * (tab:elapse), which times RK4 steps of fixed rule on the same rays in
+ * Cartesian Kerr-Schild and in Boyer-Lindquist coordinates (the line element
+ * at the start of Sec. 2.1), with the state stored structure-of-arrays or
+ * array-of-structures, in single or double precision.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t rhs_form;  /* KH_RHS_FACTORED or KH_RHS_PAPER: Cartesian Kerr-Schild states
+                        (t, x, y, z, k^t, k^x, k^y, k^z); KH_RHS_BL: Boyer-Lindquist states
+                        (t, r, theta, phi, k^t, k^r, k^theta, k^phi) */
+  int32_t layout;    /* KH_SOA: component c of geodesic i at y[c n + i]; KH_AOS: at y[8 i + c] */
+  int32_t precision; /* KH_P64: y holds doubles; KH_P32: floats, and all arithmetic in FP32 */
+  int32_t nsteps;    /* steps per geodesic in this call, >= 0 */
+  double spin;       /* chart spin a, common to every geodesic; |a| < 1 */
+  double h_coeff;    /* step h = h_coeff * r, r at the start of the step; > 0 */
+  double r_stop;     /* KH_CAPTURED once r < r_stop after a step */
+  double r_escape;   /* KH_ESCAPED once r > r_escape and dr/dlambda > 0 after a step */
+} kh_fixed_params;
+
+/* Up to p->nsteps classic RK4 steps (four right-hand-side evaluations each, no
+ * error control) for every geodesic i < n with status[i] == KH_ACTIVE.  After
+ * each step: a NaN component makes it KH_FAILED, then the r_stop and r_escape
+ * tests apply (r is the Boyer-Lindquist radius in both charts); steps[i] is
+ * increased by the steps taken.  y: device array of 8 n values in p's
+ * precision and layout (8-byte, or 4-byte for FP32, aligned); status, steps:
+ * device int32 [n].  One geodesic per lane and no refill, so a wave runs as
+ * long as its longest geodesic.  Asynchronous; allocates nothing.  Calls
+ * resume exactly where the previous one stopped.  KH_EINVAL for bad
+ * arguments (checked before any launch). */
+kh_status kh_rk4_fixed(kh_ctx *ctx, const kh_fixed_params *p, void *y, int32_t *status, int32_t *steps,
+                       int64_t n, void *stream);
+
+/* Kerr-Schild states s (device double [8][n], as kh_state.s) converted to the
+ * chart, precision and layout of p and written to y (device, 8 n values); for
+ * the Kerr-Schild forms a copy.  KH_RHS_BL (needs |p->spin| < 1 and every r
+ * above the outer horizon): r from eq:CKSr, theta = atan2(sqrt(x^2 + y^2) /
+ * sqrt(r^2 + a^2), z / r), phi = atan2(y, x) - atan2(a, r) - G(r),
+ * t = T - F(r), with F(r) = int 2r/Delta dr and G(r) = int a/Delta dr (the
+ * ingoing Kerr-Schild shifts, integration constants as in
+ * 2 (r_+ ln|r - r_+| - r_- ln|r - r_-|) / (r_+ - r_-) and
+ * a ln|(r - r_+)/(r - r_-)| / (r_+ - r_-)); the momentum by the inverse
+ * Jacobian of that map.  Conversion in FP64, then rounded to p's precision. */
+kh_status kh_pack_fixed(kh_ctx *ctx, const kh_fixed_params *p, const double *s, void *y, int64_t n,
+                        void *stream);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,8 @@ ACTIVE, CAPTURED, ESCAPED, T_END, MAX_STEPS, FAILED = range(6)
 NULL, TIMELIKE = 0, 1
 RK4, DOPRI5, DOPRI5_T = 0, 1, 2
 P64, P32, PMIXED = 0, 1, 2
-RHS_FACTORED, RHS_PAPER = 0, 1
+RHS_FACTORED, RHS_PAPER, RHS_BL = 0, 1, 2
+SOA, AOS = 0, 1
 
 
 class kh_camera(C.Structure):
@@ -50,7 +51,12 @@ class kh_params(C.Structure):
 class kh_flop_counts(C.Structure):
     _fields_ = [("add", C.c_int64), ("mul", C.c_int64), ("div", C.c_int64), ("sqrt", C.c_int64),
                 ("step_add", C.c_int64), ("step_mul", C.c_int64), ("step_div", C.c_int64),
-                ("step_sqrt", C.c_int64)]
+                ("step_sqrt", C.c_int64), ("trig", C.c_int64)]
+
+
+class kh_fixed_params(C.Structure):
+    _fields_ = [("rhs_form", C.c_int32), ("layout", C.c_int32), ("precision", C.c_int32), ("nsteps", C.c_int32),
+                ("spin", C.c_double), ("h_coeff", C.c_double), ("r_stop", C.c_double), ("r_escape", C.c_double)]
 
 
 class kh_mlp(C.Structure):
@@ -68,7 +74,8 @@ MLP_WB_ELEMS = 208896
 MLP_WBT_ELEMS = 204800
 
 EXPORTS = ["kh_create", "kh_destroy", "kh_last_error", "kh_default_params", "kh_init_rays", "kh_init_rays_list",
-           "kh_init_geodesics", "kh_integrate", "kh_read_state", "kh_stats", "kh_stats_device", "kh_rhs", "kh_flops"]
+           "kh_init_geodesics", "kh_integrate", "kh_read_state", "kh_stats", "kh_stats_device", "kh_rhs", "kh_flops",
+           "kh_rk4_fixed", "kh_pack_fixed"]
 MLP_EXPORTS = ["kh_mlp_work_bytes", "kh_mlp_sync", "kh_mlp_forward", "kh_mlp_image", "kh_mlp_targets", "kh_mlp_grad",
                "kh_mlp_train_step", "kh_init_rays_pixels", "kh_image_from_state"]
 
@@ -100,6 +107,8 @@ def lib():
         L.kh_stats_device.argtypes = [vp, P(kh_state), vp, vp]
         L.kh_rhs.argtypes = [vp, i32, i32, vp, vp, vp, i64, vp]
         L.kh_flops.argtypes = [i32, i32, P(kh_flop_counts)]
+        L.kh_rk4_fixed.argtypes = [vp, P(kh_fixed_params), vp, vp, vp, i64, vp]
+        L.kh_pack_fixed.argtypes = [vp, P(kh_fixed_params), vp, vp, i64, vp]
         L.kh_mlp_work_bytes.argtypes = [i32]
         L.kh_mlp_work_bytes.restype = i64
         L.kh_mlp_sync.argtypes = [vp, P(kh_mlp), vp]
@@ -234,6 +243,61 @@ class Context:
         self._check(lib().kh_rhs(self.handle, precision, rhs_form, spin_chart.data_ptr(), s.data_ptr(),
                                  acc.data_ptr(), n, _stream(stream)), "kh_rhs")
         return acc
+
+
+    def kh_pack_fixed(self, params: kh_fixed_params, s, y, stream=None):
+        """Kerr-Schild states s (float64 CUDA tensor (8, n)) into y, a CUDA
+        tensor of 8 n values in the chart, precision and layout of params."""
+        n = s.shape[1] if s.dim() == 2 else 0
+        if s.dtype != torch.float64 or tuple(s.shape) != (8, n) or not s.is_contiguous() or not s.is_cuda:
+            raise ValueError("s must be a contiguous float64 CUDA tensor of shape (8, n)")
+        _check_fixed_y(params, y, n)
+        self._check(lib().kh_pack_fixed(self.handle, C.byref(params), s.data_ptr(), y.data_ptr(), n,
+                                        _stream(stream)), "kh_pack_fixed")
+
+    def kh_rk4_fixed(self, params: kh_fixed_params, y, status, steps, stream=None):
+        """params.nsteps RK4 steps on y (8 n values, chart / precision / layout
+        of params); status and steps: int32 CUDA tensors of n elements."""
+        n = status.numel()
+        for t in (status, steps):
+            if t.dtype != torch.int32 or not t.is_cuda or t.numel() != n or not t.is_contiguous():
+                raise ValueError("status and steps must be contiguous int32 CUDA tensors of one length")
+        _check_fixed_y(params, y, n)
+        self._check(lib().kh_rk4_fixed(self.handle, C.byref(params), y.data_ptr(), status.data_ptr(),
+                                       steps.data_ptr(), n, _stream(stream)), "kh_rk4_fixed")
+
+
+class FixedState:
+    """Device arrays of ``kh_rk4_fixed`` for the n geodesics of Kerr-Schild
+    states ``s_ks`` (float64 CUDA (8, n), e.g. ``State.s`` after an init call),
+    converted by ``kh_pack_fixed`` to the chart, precision and layout of
+    ``params``.  ``status`` starts as given (default all active)."""
+
+    def __init__(self, ctx: "Context", params: kh_fixed_params, s_ks, status=None, stream=None):
+        n = s_ks.shape[1]
+        self.n = n
+        self.params = params
+        dt = torch.float64 if params.precision == P64 else torch.float32
+        self.y = torch.empty(8 * n, dtype=dt, device=s_ks.device)
+        i32 = dict(dtype=torch.int32, device=s_ks.device)
+        self.status = torch.zeros(n, **i32) if status is None else status.to(**i32).clone()
+        self.steps = torch.zeros(n, **i32)
+        ctx.kh_pack_fixed(params, s_ks, self.y, stream)
+
+    def components(self):
+        """(8, n) view of y whatever its layout."""
+        return self.y.view(8, self.n) if self.params.layout == SOA else self.y.view(self.n, 8).t()
+
+
+def fixed_params(rhs_form=RHS_FACTORED, layout=SOA, precision=P64, nsteps=1024, spin=0.0, h_coeff=1.0 / 256,
+                 r_stop=0.0, r_escape=1e30) -> kh_fixed_params:
+    return kh_fixed_params(rhs_form, layout, precision, nsteps, spin, h_coeff, r_stop, r_escape)
+
+
+def _check_fixed_y(params, y, n):
+    dt = {P64: torch.float64, P32: torch.float32}.get(params.precision, y.dtype)  # else the library refuses
+    if y.dtype != dt or not y.is_cuda or y.numel() != 8 * n or not y.is_contiguous():
+        raise ValueError(f"y must be a contiguous {dt} CUDA tensor of 8 n = {8 * n} elements")
 
 
 def _check_vec(t, n):

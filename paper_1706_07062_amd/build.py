@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkerrhip.so")
-SOURCES = ["kerrhip.hip", "mlp.hip"]
+SOURCES = ["kerrhip.hip", "mlp.hip", "fixed.hip"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
 # -ffp-contract=on: fuse multiply-adds per source expression, so every inlined

@@ -843,7 +843,7 @@ __global__ void k_stats(const int32_t* status, const int32_t* n_acc, const int32
 // Host-side operation counter for kh_flops.
 // ---------------------------------------------------------------------------
 struct Tally {
-  int64_t add = 0, mul = 0, div = 0, sqrt = 0;
+  int64_t add = 0, mul = 0, div = 0, sqrt = 0, trig = 0;
 };
 thread_local Tally* g_tally = nullptr;
 
@@ -887,6 +887,11 @@ inline Cnt krcp(Cnt x) {
 inline Cnt krcp_est(Cnt x) {
   ++g_tally->div;
   return Cnt(1.0 / x.v);
+}
+inline void ksincos(Cnt x, Cnt* sn, Cnt* cs) {
+  g_tally->trig += 2;
+  *sn = Cnt(std::sin(x.v));
+  *cs = Cnt(std::cos(x.v));
 }
 inline Cnt kabs(Cnt x) { return Cnt(std::fabs(x.v)); }
 inline Cnt kmax(Cnt x, Cnt y) { return x.v > y.v ? x : y; }
@@ -1425,9 +1430,25 @@ kh_status kh_rhs(kh_ctx* ctx, int32_t precision, int32_t rhs_form, const double*
 
 kh_status kh_flops(int32_t method, int32_t rhs_form, kh_flop_counts* out) {
   if (!out || (method != KH_RK4 && method != KH_DOPRI5 && method != KH_DOPRI5_T) ||
-      (rhs_form != KH_RHS_FACTORED && rhs_form != KH_RHS_PAPER) ||
-      (method == KH_DOPRI5_T && rhs_form != KH_RHS_FACTORED))
+      (rhs_form != KH_RHS_FACTORED && rhs_form != KH_RHS_PAPER && rhs_form != KH_RHS_BL) ||
+      (method == KH_DOPRI5_T && rhs_form != KH_RHS_FACTORED) || (rhs_form == KH_RHS_BL && method != KH_RK4))
     return KH_EINVAL;
+  if (rhs_form == KH_RHS_BL) {
+    // Boyer-Lindquist point (t, r, theta, phi) off the equator and the poles
+    Tally tb, ts;
+    const Cnt xb[4] = {Cnt(0.0), Cnt(7.0), Cnt(1.1), Cnt(0.3)};
+    const Cnt kb[4] = {Cnt(1.2), Cnt(-0.6), Cnt(0.03), Cnt(-0.02)};
+    const Cnt a1[4] = {Cnt(0.01), Cnt(0.02), Cnt(-0.01), Cnt(0.005)};
+    Cnt xn[4], kn[4];
+    g_tally = &tb;
+    (void)chart_rhs<KH_RHS_BL, Cnt>(Cnt(0.9), xb, kb);
+    g_tally = &ts;
+    rk4_step<KH_RHS_BL, Cnt, Cnt>(Cnt(0.9), xb, kb, a1, Cnt(0.1), xn, kn);
+    g_tally = nullptr;
+    *out = kh_flop_counts{tb.add, tb.mul, tb.div, tb.sqrt, ts.add - 3 * tb.add, ts.mul - 3 * tb.mul,
+                          ts.div - 3 * tb.div, ts.sqrt - 3 * tb.sqrt, tb.trig};
+    return KH_OK;
+  }
   Tally t_rhs, t_step;
   const Cnt x[4] = {Cnt(0.0), Cnt(7.0), Cnt(-3.0), Cnt(2.0)};
   const Cnt k[4] = {Cnt(1.2), Cnt(-0.6), Cnt(0.3), Cnt(-0.2)};
@@ -1471,6 +1492,7 @@ kh_status kh_flops(int32_t method, int32_t rhs_form, kh_flop_counts* out) {
   out->step_mul = t_step.mul - n_rhs * t_rhs.mul;
   out->step_div = t_step.div - n_rhs * t_rhs.div;
   out->step_sqrt = t_step.sqrt - n_rhs * t_rhs.sqrt;
+  out->trig = 0;
   return KH_OK;
 }
 

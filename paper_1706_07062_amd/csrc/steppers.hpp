@@ -13,9 +13,20 @@
 // coefficients A A, b A and e A (e = b - b*) are folded at compile time.
 #pragma once
 
+#include "bl_math.hpp"
 #include "ks_math.hpp"
 
 namespace kh {
+
+// Right-hand side by form: 0 / 1 = Cartesian Kerr-Schild (factored / as
+// regrouped in the paper), 2 = Boyer-Lindquist (fixed-step chart comparison).
+template <int FORM, typename T>
+__host__ __device__ inline Accel<T> chart_rhs(T a, const T x[4], const T k[4]) {
+  if constexpr (FORM == 2)
+    return rhs_bl<T>(a, x, k);
+  else
+    return rhs<FORM, T>(a, x, k);
+}
 
 // Scalar helpers for the norm, dispatched on type.
 __host__ __device__ inline double kabs(double x) { return fabs(x); }
@@ -198,7 +209,7 @@ __host__ __device__ inline void rk4_step(TS a_c, const TS x[4], const TS k[4], c
 #pragma unroll
   for (int c = 0; c < 4; ++c) K[c] = Conv<TS, TR>::to(k[c] + hh * a1[c]);
   {
-    const Accel<TR> ra = rhs<FORM, TR>(ac, X, K);
+    const Accel<TR> ra = chart_rhs<FORM, TR>(ac, X, K);
 #pragma unroll
     for (int c = 0; c < 4; ++c) a2[c] = Conv<TS, TR>::from(ra.a[c]);
   }
@@ -207,7 +218,7 @@ __host__ __device__ inline void rk4_step(TS a_c, const TS x[4], const TS k[4], c
 #pragma unroll
   for (int c = 0; c < 4; ++c) K[c] = Conv<TS, TR>::to(k[c] + hh * a2[c]);
   {
-    const Accel<TR> ra = rhs<FORM, TR>(ac, X, K);
+    const Accel<TR> ra = chart_rhs<FORM, TR>(ac, X, K);
 #pragma unroll
     for (int c = 0; c < 4; ++c) a3[c] = Conv<TS, TR>::from(ra.a[c]);
   }
@@ -216,7 +227,7 @@ __host__ __device__ inline void rk4_step(TS a_c, const TS x[4], const TS k[4], c
 #pragma unroll
   for (int c = 0; c < 4; ++c) K[c] = Conv<TS, TR>::to(k[c] + h * a3[c]);
   {
-    const Accel<TR> ra = rhs<FORM, TR>(ac, X, K);
+    const Accel<TR> ra = chart_rhs<FORM, TR>(ac, X, K);
 #pragma unroll
     for (int c = 0; c < 4; ++c) a4[c] = Conv<TS, TR>::from(ra.a[c]);
   }

@@ -16,6 +16,9 @@ fixed seeds.  Names of the workloads follow what they are:
   ~ U[0, 0.998], inclination ~ U[5, 85] deg, [-12, 12]^2, observer at 1000 M.
 * ``surrogate_rays``: rays with alpha, beta ~ U[-12, 12], a ~ U[0, 0.998],
   inclination ~ U[5, 85] deg; evaluation image 4096x4096 at a = 0.9, 45 deg.
+* ``elapse_image``: a = 0.999, image at r = 1024 M, inclination 60 deg,
+  [-12, 12]^2, fixed-step RK4 (h = r / 256) in launches of 1024 steps, in
+  Kerr-Schild and Boyer-Lindquist coordinates.
 """
 from __future__ import annotations
 
@@ -55,6 +58,18 @@ def schwarzschild_64() -> Camera:
 
 def kerr_image(incl_deg: float, side: int = 1024, a: float = 0.99) -> Camera:
     return Camera(a, 1000.0, incl_deg, -12.0, 12.0, -12.0, 12.0, side, side)
+
+
+# Chart / data-layout comparison of Sec. 4 (tab:elapse): an image at r = 1024
+# toward a hole of spin 0.999, fixed-step RK4 in launches of 1024 steps.  The
+# inclination and the image field are not stated there; 60 degrees and
+# [-12, 12]^2 (the field of the images above) are taken.
+ELAPSE_STEPS = 1024
+ELAPSE_H_COEFF = 1.0 / 256  # no ray reaches r < 18 or turns back within one launch
+
+
+def elapse_image(side: int = 1024) -> Camera:
+    return Camera(0.999, 1024.0, 60.0, -12.0, 12.0, -12.0, 12.0, side, side)
 
 
 def kerr_1024() -> list[Camera]:

@@ -1,5 +1,5 @@
-// Host instantiation of the GPU library's device templates (right-hand side,
-// Runge-Kutta steps, Hermite root), so CPU tests can compare that arithmetic
+// Host instantiation of the GPU library's device templates (right-hand sides
+// in both charts, Runge-Kutta steps, Hermite root), so CPU tests can compare that arithmetic
 // with the oracle without a GPU.  Test-only; not part of the library.
 #include "ks_math.hpp"
 #include "steppers.hpp"
@@ -13,12 +13,16 @@ void host_rhs(int form, int fp32, double a, const double* x, const double* k, do
       xf[c] = (float)x[c];
       kf[c] = (float)k[c];
     }
-    kh::Accel<float> r = form ? kh::rhs<1, float>((float)a, xf, kf) : kh::rhs<0, float>((float)a, xf, kf);
+    kh::Accel<float> r = form == 2   ? kh::chart_rhs<2, float>((float)a, xf, kf)
+                         : form == 1 ? kh::chart_rhs<1, float>((float)a, xf, kf)
+                                     : kh::chart_rhs<0, float>((float)a, xf, kf);
     for (int c = 0; c < 4; ++c) acc[c] = r.a[c];
     acc[4] = r.r;
     acc[5] = r.rdot;
   } else {
-    kh::Accel<double> r = form ? kh::rhs<1, double>(a, x, k) : kh::rhs<0, double>(a, x, k);
+    kh::Accel<double> r = form == 2   ? kh::chart_rhs<2, double>(a, x, k)
+                          : form == 1 ? kh::chart_rhs<1, double>(a, x, k)
+                                      : kh::chart_rhs<0, double>(a, x, k);
     for (int c = 0; c < 4; ++c) acc[c] = r.a[c];
     acc[4] = r.r;
     acc[5] = r.rdot;
@@ -44,6 +48,17 @@ void host_rk4(double a, const double* x, const double* k, double h, double* out)
   kh::Accel<double> r1 = kh::rhs<0, double>(a, x, k);
   double xn[4], kn[4];
   kh::rk4_step<0, double, double>(a, x, k, r1.a, h, xn, kn);
+  for (int c = 0; c < 4; ++c) {
+    out[c] = xn[c];
+    out[4 + c] = kn[c];
+  }
+}
+
+// One RK4 step in the Boyer-Lindquist chart: out = (xn[4], kn[4]).
+void host_rk4_bl(double a, const double* x, const double* k, double h, double* out) {
+  kh::Accel<double> r1 = kh::chart_rhs<2, double>(a, x, k);
+  double xn[4], kn[4];
+  kh::rk4_step<2, double, double>(a, x, k, r1.a, h, xn, kn);
   for (int c = 0; c < 4; ++c) {
     out[c] = xn[c];
     out[4 + c] = kn[c];

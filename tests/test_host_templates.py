@@ -23,7 +23,7 @@ CSRC = os.path.join(ROOT, "paper_1706_07062_amd", "csrc")
 
 @pytest.fixture(scope="module")
 def H():
-    deps = [SRC] + [os.path.join(CSRC, f) for f in ("ks_math.hpp", "steppers.hpp")]
+    deps = [SRC] + [os.path.join(CSRC, f) for f in ("ks_math.hpp", "bl_math.hpp", "steppers.hpp")]
     if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(d) for d in deps):
         subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-D__HIP_PLATFORM_AMD__",
                         "-I/opt/rocm/include", "-I" + CSRC, "-o", LIB, SRC], check=True)
@@ -32,6 +32,7 @@ def H():
     L.host_rhs.argtypes = [C.c_int, C.c_int, C.c_double, pd, pd, pd]
     L.host_dp5.argtypes = [C.c_double, pd, pd, C.c_double, C.c_double, C.c_double, pd]
     L.host_rk4.argtypes = [C.c_double, pd, pd, C.c_double, pd]
+    L.host_rk4_bl.argtypes = [C.c_double, pd, pd, C.c_double, pd]
     L.host_hermite_zero.argtypes = [C.c_double] * 5
     L.host_hermite_zero.restype = C.c_double
     L.host_constants.argtypes = [C.c_double, pd, pd, pd]
@@ -167,3 +168,54 @@ def test_azimuth_estimate_recovers_winding(H):
             phi = true + 2 * np.pi * w
             assert int(np.rint((phi - est) / (2 * np.pi))) == w, (y, x, w)
     assert worst < 0.08 + 1e-6  # away from the origin the estimate is within 0.08 rad
+
+
+# ---------------------------------------------------------------------------
+# Boyer-Lindquist form (chart comparison of Sec. 4).
+# ---------------------------------------------------------------------------
+def _bl_states(n, a):
+    out = []
+    rh = 1 + np.sqrt(1 - a * a)
+    while len(out) < n:
+        r = rh * 1.02 + rng.choice([2.0, 20.0, 1000.0]) * rng.uniform()
+        th = rng.uniform(0.05, np.pi - 0.05)
+        k = rng.normal(size=4)
+        out.append(np.array([rng.uniform(0, 10), r, th, rng.uniform(-3, 3), *k]))
+    return out
+
+
+@pytest.mark.parametrize("a", [0.0, 0.5, -0.9, 0.999])
+def test_bl_rhs_matches_oracle(H, a):
+    """The contracted Boyer-Lindquist form equals the Christoffel form on the
+    Boyer-Lindquist line element."""
+    for y in _bl_states(60, a):
+        acc = np.zeros(6)
+        H.host_rhs(2, 0, a, _p(y[:4].copy()), _p(y[4:].copy()), _p(acc))
+        want = O.bl_rhs(a, y[:4], y[4:])
+        scale = np.abs(want).max()
+        np.testing.assert_allclose(acc[:4], want, rtol=0, atol=1e-12 * scale)
+        assert acc[4] == y[1] and acc[5] == y[5]
+
+
+def test_bl_rhs_fp32_error(H):
+    a = 0.999
+    errs = []
+    for y in _bl_states(200, a):
+        a64, a32 = np.zeros(6), np.zeros(6)
+        H.host_rhs(2, 0, a, _p(y[:4].copy()), _p(y[4:].copy()), _p(a64))
+        H.host_rhs(2, 1, a, _p(y[:4].copy()), _p(y[4:].copy()), _p(a32))
+        errs.append(np.abs(a32[:4] - a64[:4]).max() / np.abs(a64[:4]).max())
+    assert np.median(errs) < 1e-5
+
+
+def test_bl_rk4_step_matches_oracle(H):
+    a = -0.999
+    for y in _bl_states(30, abs(a)):
+        y[6:] /= y[1]  # angular rates of order 1/r, as for a ray of unit energy
+        hc = 1 / 64
+        out = np.zeros(8)
+        H.host_rk4_bl(a, _p(y[:4].copy()), _p(y[4:].copy()), hc * y[1], _p(out))
+        want, st, _ = O.rk4_fixed("bl", a, hc, 0.0, 1e30, 1, y[:, None])
+        if st[0] != O.ACTIVE:
+            continue
+        np.testing.assert_allclose(out, want[:, 0], rtol=1e-11, atol=1e-11 * np.abs(y).max())

@@ -54,6 +54,8 @@ def test_default_params_and_struct_layout():
     assert C.sizeof(K.kh_camera) == 64
     assert C.sizeof(K.kh_params) == 112
     assert C.sizeof(K.kh_state) == 8 * 19
+    assert C.sizeof(K.kh_flop_counts) == 8 * 9
+    assert C.sizeof(K.kh_fixed_params) == 16 + 8 * 4
 
 
 def test_flop_counts():
@@ -73,3 +75,12 @@ def test_flop_counts():
     assert f["step_add"] > 100 and f["step_mul"] > 100 and f["step_sqrt"] == 0
     r = K.kh_flops(K.RK4, K.RHS_FACTORED)
     assert r["step_add"] > 20
+    assert f["trig"] == 0 and r["trig"] == 0
+    # Boyer-Lindquist form: one sin and one cos, one reciprocal (1/rho^2,
+    # 1/Delta, 1/sin^2 from their product), no root; the same RK4 step
+    b = K.kh_flops(K.RK4, K.RHS_BL)
+    assert b["trig"] == 2 and b["sqrt"] == 0 and b["div"] == 1
+    assert 80 < b["add"] + b["mul"] < 400
+    assert (b["step_add"], b["step_mul"]) == (r["step_add"], r["step_mul"])
+    with pytest.raises(K.KerrHipError):
+        K.kh_flops(K.DOPRI5, K.RHS_BL)
