@@ -7,7 +7,9 @@
 // [ray][feature]).  The 32x32 accumulator then holds, per lane, four
 // consecutive output features of one ray, so bias, SiLU and the BF16 store of
 // the next activation row are one 8-byte write.  One wave owns 32 rays and
-// carries them through all five layers without leaving the CU.
+// carries them through all five layers without leaving the CU.  (Training
+// keeps the activations in that LDS tile; inference, k_mlp_fwd_reg, keeps
+// them in registers and stages only weights through LDS.)
 //
 // MFMA operand layout used (v_mfma_f32_32x32x16_bf16, 64 lanes):
 //   A[i][k]: lane l holds i = l % 32, k = 8 (l / 32) + j, j = 0..7
@@ -218,115 +220,6 @@ __global__ void __launch_bounds__(64) k_mlp_fwd(FwdArgs A) {
   }
   if (MODE == 1) {
     // wave-aggregated append of the uncertain pixels
-    const unsigned long long mask = __ballot(unsure);
-    if (mask) {
-      const int leader = __ffsll((long long)mask) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(A.fb_count, __popcll(mask));
-      base = __shfl(base, leader);
-      if (unsure) {
-        const unsigned rank =
-            __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-        A.fb_ids[base + rank] = (int32_t)ray;
-      }
-    }
-  }
-}
-
-// Inference forward for a block of four waves (128 rays).  The hidden layers'
-// weights are staged through LDS one 256 x 16 slab at a time, so each slab is
-// read from L2 once per 128 rays instead of once per 32, and the next slab is
-// loaded into registers while the current one feeds the MFMAs.
-// LDS: 4 activation tiles (66 KB) + one slab (12 KB) < 80 KB, two blocks per CU.
-constexpr int WROW = 24;  // slab row stride (BF16): 48 bytes spreads rows over the banks
-
-template <int MODE>
-__global__ void __launch_bounds__(256) k_mlp_fwd4(FwdArgs A) {
-  __shared__ __attribute__((aligned(16))) __bf16 act_all[4 * RAYS * LDA];
-  __shared__ __attribute__((aligned(16))) __bf16 wsl[HID * WROW];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = lane & 31, half = lane >> 5;
-  __bf16* act = act_all + w * RAYS * LDA;
-  const int64_t ray = (int64_t)blockIdx.x * (4 * RAYS) + w * RAYS + r;
-  const bool valid = ray < A.m;
-
-  float f[4] = {0.f, 0.f, 0.f, 0.f};
-  if (valid) {
-    if (MODE == 1) {
-      const int64_t row = ray / A.cam.width, col = ray % A.cam.width;
-      const float al = (float)(A.cam.alpha_min + (col + 0.5) * (A.cam.alpha_max - A.cam.alpha_min) / A.cam.width);
-      const float be = (float)(A.cam.beta_min + (row + 0.5) * (A.cam.beta_max - A.cam.beta_min) / A.cam.height);
-      norm_features(al, be, (float)A.cam.a, (float)A.cam.incl, f);
-    } else {
-      const f32x4 xv = *reinterpret_cast<const f32x4*>(A.x + ray * 4);
-      norm_features(xv[0], xv[1], xv[2], xv[3], f);
-    }
-  }
-  bf16x8 bx;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) bx[j] = (half == 0 && j < 4) ? (__bf16)f[j] : (__bf16)0.0f;
-  f32x16 acc[8];
-  const f32x16 zero = {};
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[0] + (t * 32 + r) * KPAD[0] + 8 * half);
-    acc[t] = mfma(aw, bx, zero);
-  }
-  store_hidden<MODE>(A, 0, acc, act, r, half, ray, valid);
-
-  for (int l = 1; l < 4; ++l) {
-    const __bf16* wg = A.wb + (l == 1 ? OFF_WB[1] : l == 2 ? OFF_WB[2] : OFF_WB[3]) + tid * HID;
-    bf16x8 p0 = *reinterpret_cast<const bf16x8*>(wg);
-    bf16x8 p1 = *reinterpret_cast<const bf16x8*>(wg + 8);
-#pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] = zero;
-    wave_sync();
-    for (int ks = 0; ks < HID / 16; ++ks) {
-      __syncthreads();  // the previous slab is no longer read
-      *reinterpret_cast<bf16x8*>(wsl + tid * WROW) = p0;
-      *reinterpret_cast<bf16x8*>(wsl + tid * WROW + 8) = p1;
-      __syncthreads();  // this slab is complete
-      if (ks + 1 < HID / 16) {
-        p0 = *reinterpret_cast<const bf16x8*>(wg + (ks + 1) * 16);
-        p1 = *reinterpret_cast<const bf16x8*>(wg + (ks + 1) * 16 + 8);
-      }
-      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(act + r * LDA + ks * 16 + 8 * half);
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const bf16x8 aw = *reinterpret_cast<const bf16x8*>(wsl + (t * 32 + r) * WROW + 8 * half);
-        acc[t] = mfma(aw, bv, acc[t]);
-      }
-    }
-    wave_sync();
-    store_hidden<MODE>(A, l, acc, act, r, half, ray, valid);
-  }
-
-  wave_sync();
-  f32x16 o = zero;
-  for (int ks = 0; ks < HID / 16; ++ks) {
-    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(act + r * LDA + ks * 16 + 8 * half);
-    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + r * HID + ks * 16 + 8 * half);
-    o = mfma(aw, bv, o);
-  }
-  bool unsure = false;
-  if (half == 0 && valid) {
-    const float* b4 = A.params + OFF_B[4];
-    f32x4 y;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) y[q] = o[q] + b4[q];
-    if (MODE == 1) {
-      const float pc = sigmoidf(y[3]);
-      f32x4 d;
-      d[0] = __expf(2.0f * y[0] + 2.0f);
-      d[1] = 3.14159265358979f * y[1];
-      d[2] = 0.3f * y[2] + 0.8f;
-      d[3] = pc;
-      *reinterpret_cast<f32x4*>(A.y + ray * 4) = d;
-      unsure = pc > A.tau && pc < 1.0f - A.tau;
-    } else {
-      *reinterpret_cast<f32x4*>(A.y + ray * 4) = y;
-    }
-  }
-  if (MODE == 1) {
     const unsigned long long mask = __ballot(unsure);
     if (mask) {
       const int leader = __ffsll((long long)mask) - 1;
