@@ -90,6 +90,58 @@ def test_gradient_matches_reference(ctx):
             off += size
 
 
+def test_image_kernel_decodes_forward_and_lists_fallback(ctx):
+    """The camera-image kernel on a ragged 37x23 camera (6 full blocks of 128
+    rays + 83): its decoded outputs equal the forward kernel's raw outputs,
+    decoded on the host, on the same pixel features; they match the FP64
+    reference with BF16 storage; and the fallback list is exactly the set of
+    pixels whose capture probability lies in (tau, 1 - tau), in any order."""
+    say("mlp image kernel")
+    p = S.init_params(12)
+    p[M.NPARAMS - 4:] = [0.2, -0.1, 0.05, 0.3]
+    net = K.Mlp(p, train=False)
+    ctx.kh_mlp_sync(net)
+    cam = W.Camera(0.9, 1000.0, 45.0, -12.0, 12.0, -9.0, 9.0, 37, 23)
+    n = cam.n
+    col, row = np.arange(n) % cam.width, np.arange(n) // cam.width
+    al = cam.alpha_min + (col + 0.5) * (cam.alpha_max - cam.alpha_min) / cam.width
+    be = cam.beta_min + (row + 0.5) * (cam.beta_max - cam.beta_min) / cam.height
+    x = np.stack([al, be, np.full(n, cam.a), np.full(n, cam.incl)], axis=1).astype(np.float32)
+    raw = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    ctx.kh_mlp_forward(net, torch.from_numpy(x).cuda(), raw)
+    raw = raw.cpu().numpy().astype(np.float64)
+    for tau in (0.2, 0.45, 0.0):
+        out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        ids = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ctx.kh_mlp_image(net, S.camera_struct(cam), tau, out, ids, cnt)
+        img = out.cpu().numpy().astype(np.float64)
+        dec = np.stack([np.exp(2 * raw[:, 0] + 2), np.pi * raw[:, 1], 0.3 * raw[:, 2] + 0.8,
+                        1 / (1 + np.exp(-raw[:, 3]))], axis=1)
+        np.testing.assert_allclose(img, dec, rtol=2e-6, atol=2e-6)
+        k = int(cnt.item())
+        listed = np.sort(ids.cpu().numpy()[:k])
+        pc = img[:, 3]
+        want = np.nonzero((pc > tau) & (pc < 1 - tau))[0]
+        say(f"  tau {tau}: {k} fallback pixels")
+        assert np.array_equal(listed, want)
+    ref, _ = M.forward(p.astype(np.float64), x.astype(np.float64), bf16_storage=True)
+    assert np.abs(raw - ref).max() / np.abs(ref).max() < 2e-2
+
+
+def test_forward_single_ray_and_one_past_a_block(ctx):
+    p = S.init_params(13)
+    net = K.Mlp(p, train=False)
+    ctx.kh_mlp_sync(net)
+    x, _, _ = _batch(129)
+    full = torch.empty((129, 4), dtype=torch.float32, device="cuda")
+    ctx.kh_mlp_forward(net, torch.from_numpy(x).cuda(), full)
+    for m in (1, 128, 129):
+        y = torch.full((m, 4), float("nan"), dtype=torch.float32, device="cuda")
+        ctx.kh_mlp_forward(net, torch.from_numpy(x[:m].copy()).cuda(), y)
+        assert torch.equal(y, full[:m])
+
+
 def test_training_and_fallback_image(ctx):
     """Train on 2^18 integrated rays for 600 steps, then render a 256x256 image
     at a = 0.9, i = 45 deg: the loss falls, the fallback integrates a minority
