@@ -18,7 +18,7 @@ with open(__file__.replace("test_gpu_convergence.py", "golden/tab_tests.txt")) a
         if line.startswith("#") or not line.strip():
             continue
         lab, a, r, phi, q, mc, dphi = line.split()
-        TAB[lab] = dict(a=float(a), r=float(r))
+        TAB[lab] = dict(a=float(a), r=float(r), dphi=float(dphi))
 
 
 def say(msg):
@@ -69,4 +69,41 @@ def test_rk4_null_norm_converges_fourth_order_on_gpu(label):
     say(f"  {label}: |g k k| after lambda = 8: {mu2}")
     r1, r2 = mu2[0] / mu2[1], mu2[1] / mu2[2]
     assert 10 < r1 < 24 and 10 < r2 < 24, (mu2, r1, r2)
+    ctx.close()
+
+
+@pytest.mark.parametrize("label", ["C", "D", "E", "F"])
+def test_tab_tests_azimuth_advance_on_gpu(label):
+    """Table tab:tests' last column on the GPU: the azimuth advance over one
+    latitude period, read from the library's equatorial-crossing records (the
+    second crossing after an upward start on the equator closes the period) of
+    a DOPRI5 run at rtol = atol = 1e-11 with steps capped at 0.02 r.  Test C
+    passes the poles, where the Cartesian azimuth jumps by pi, so it is
+    compared modulo pi."""
+    torch.cuda.set_device(0)
+    ctx = K.Context(0)
+    a, r, x3, v3, _ = launch_state(label)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    st = K.State(1, k_cross=4)
+    ctx.kh_init_geodesics(K.NULL, torch.tensor([-a], **f64), torch.tensor(x3, **f64).reshape(3, 1).contiguous(),
+                          torch.tensor(v3, **f64).reshape(3, 1).contiguous(), st)
+    p = K.kh_default_params(method=K.DOPRI5, rtol=1e-11, atol=1e-11, hmax_coeff=0.02, r_escape=1e30, r_h_factor=0.5,
+                            max_steps=400, k_cross=4)
+    ctx.kh_integrate(p, st)
+    g = st.numpy()
+    # 400 steps of at most 0.02 r reach lambda ~ 25, past one latitude period
+    # (the orbits are unstable and leave the sphere later)
+    assert g["n_cross"][0] >= 2
+    dphi = g["cross"][0, 1, 1]
+    want = cf.spherical_dphi(r, a)
+    printed = TAB[label]["dphi"]
+    d_cf, d_pr = dphi - want, dphi - printed
+    if label == "C":
+        d_cf = (d_cf + np.pi / 2) % np.pi - np.pi / 2
+        d_pr = (d_pr + np.pi / 2) % np.pi - np.pi / 2
+    say(f"  {label}: dphi {dphi:.8f} (closed form {want:.8f}, printed {printed}); crossing r {g['cross'][0, 1, 0]:.8f}")
+    assert abs(d_cf) < 1e-6
+    assert abs(d_pr) <= 5e-5 + 1e-6  # the table prints four decimals
+    # the crossing radius is the orbit's Boyer-Lindquist radius
+    assert g["cross"][0, 1, 0] == pytest.approx(r, rel=1e-7)
     ctx.close()
