@@ -107,3 +107,37 @@ def test_tab_tests_azimuth_advance_on_gpu(label):
     # the crossing radius is the orbit's Boyer-Lindquist radius
     assert g["cross"][0, 1, 0] == pytest.approx(r, rel=1e-7)
     ctx.close()
+
+
+@pytest.mark.parametrize("r", [1.3, 1.5, 3.0])
+def test_vertical_epicyclic_frequency_on_gpu(r):
+    """The time-like test of Sec. 3.2 (Fig. OmegaV) on the GPU: a = 1, a
+    circular equatorial orbit nudged with v_z = 1e-12.  On a circular orbit
+    phi = Omega t, so the azimuth between successive equatorial crossings,
+    read from the library's crossing records, is Omega pi / Omega_z; Omega_z
+    matches the closed form."""
+    torch.cuda.set_device(0)
+    ctx = K.Context(0)
+    a = 1.0
+    om = cf.omega_kepler(r, a)
+    rho = np.sqrt(r * r + a * a)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    st = K.State(1, k_cross=8)
+    x3 = torch.tensor([[rho], [0.0], [0.0]], **f64)
+    v3 = torch.tensor([[0.0], [om * rho], [1e-12]], **f64)
+    ctx.kh_init_geodesics(K.TIMELIKE, torch.tensor([a], **f64), x3, v3, st)
+    want = cf.omega_vertical(r, a)
+    # the relative tolerance on the 1e-12 vertical motion keeps the steps
+    # short: about 4000 per vertical period at r = 1.3, so 24000 cover the
+    # four periods (eight crossings) needed at every radius here
+    p = K.kh_default_params(method=K.DOPRI5, rtol=1e-12, atol=1e-30, hmax_coeff=0.05, r_escape=1e4, r_h_factor=0.5,
+                            max_steps=24000, k_cross=8)
+    ctx.kh_integrate(p, st)
+    g = st.numpy()
+    assert g["status"][0] == K.MAX_STEPS and g["n_cross"][0] >= 8
+    phis = g["cross"][0, :, 1]
+    half = np.diff(phis).mean()
+    got = np.pi * om / half
+    say(f"  r = {r}: Omega_z {got:.12f}, closed form {want:.12f}, rel {abs(got / want - 1):.2e}")
+    assert got == pytest.approx(want, rel=1e-8)
+    ctx.close()
