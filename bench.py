@@ -64,7 +64,7 @@ def algorithmic_flops(K, stats, n_rays, method, form):
     rhs = f["add"] + f["mul"] + f["div"] + f["sqrt"]
     step = f["step_add"] + f["step_mul"] + f["step_div"] + f["step_sqrt"]
     attempts = stats["n_acc"] + stats["n_rej"]
-    if method == K.DOPRI5:
+    if method in (K.DOPRI5, K.DOPRI5_T):
         n_rhs = 6 * attempts + n_rays
         flops = attempts * (6 * rhs + step) + n_rays * rhs
     else:
@@ -174,9 +174,12 @@ def extras(args, ctx, K, W, torch):  # noqa: C901
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         s = ctx.kh_stats(st)
+        flops = algorithmic_flops(K, s, n, method, K.RHS_FACTORED)[0]
+        tf = flops / dt / 1e12
         res[name] = dict(rays_per_s=n / dt, kernel_ms=dt * 1e3, rtol=tol,
-                         rhs_evals_per_s=(6 * (s["n_acc"] + s["n_rej"]) + n) / dt)
-        log(f"{name}: {n / dt:.3e} rays/s")
+                         rhs_evals_per_s=(6 * (s["n_acc"] + s["n_rej"]) + n) / dt, alg_tflops=tf,
+                         frac_fp64_peak=tf / FP64_PEAK_TFLOPS, frac_fp32_peak=tf / FP32_PEAK_TFLOPS)
+        log(f"{name}: {n / dt:.3e} rays/s, {tf:.1f} TFLOP/s")
     # Fixed-step RK4 (h = 0.01 r) on the paper's benchmark geometry: a = 0.999,
     # image at r = 1024 M, 1024x1024.
     cam = W.Camera(0.999, 1024.0, 60.0, -12, 12, -12, 12, 1024, 1024)
