@@ -36,7 +36,8 @@ constexpr int NP = KH_MLP_NPARAMS;
 constexpr int HID = 256;
 constexpr int RAYS = 32;        // rays per wave
 constexpr int LDA = HID + 8;    // LDS row stride (BF16) of the activation tile
-constexpr int SPLITS = 16;      // batch splits of the weight-gradient products
+constexpr int SPLITS = 16;      // batch splits of the weight-gradient products (a multiple of 8)
+static_assert(SPLITS % 8 == 0, "two or more whole splits per XCD");
 constexpr int HT0_ROWS = 32;    // input features padded to one 32-row tile
 
 // FP32 parameter offsets: W_l [out][in], then b_l.
@@ -464,6 +465,7 @@ __global__ void __launch_bounds__(64) k_mlp_bwd_dx(const __bf16* wbt, int opad, 
   const f32x16 zero = {};
 #pragma unroll
   for (int t = 0; t < 8; ++t) acc[t] = zero;
+#pragma unroll 4
   for (int os = 0; os < opad / 16; ++os) {
     const bf16x8 bv = *reinterpret_cast<const bf16x8*>(dz + ray * opad + os * 16 + 8 * half);
 #pragma unroll
@@ -495,17 +497,33 @@ __global__ void __launch_bounds__(64) k_mlp_bwd_dw(const __bf16* dzT, int opad, 
                                                     int nin, int64_t bmax, int64_t b, float* part, int off_w,
                                                     int off_b) {
   const int lane = threadIdx.x, r = lane & 31, half = lane >> 5;
-  const int tiles_i = ipad / 32;
-  const int ot = blockIdx.x / tiles_i, it = blockIdx.x % tiles_i;
-  const int s = blockIdx.y;
+  const int tiles_i = ipad / 32, tiles = gridDim.x / SPLITS;
+  // Workgroups go to the 8 XCDs round-robin by linear id; give each XCD two
+  // whole batch splits (all output tiles of them), so that an XCD's L2 holds
+  // only its 1/8 of dz^T and h instead of every tile's re-read of all of it.
+  const int xcd = blockIdx.x % 8, j = blockIdx.x / 8;
+  const int s = xcd * (SPLITS / 8) + j / tiles;
+  const int tile = j % tiles;
+  const int ot = tile / tiles_i, it = tile % tiles_i;
   const int64_t per = b / SPLITS;
   const int64_t b0 = s * per, b1 = b0 + per;
   f32x16 acc = {};
-  for (int64_t kb = b0; kb < b1; kb += 16) {
-    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(dzT + (int64_t)(ot * 32 + r) * bmax + kb + 8 * half);
-    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(ht + (int64_t)(it * 32 + r) * bmax + kb + 8 * half);
-    acc = mfma(aw, bv, acc);
+  const __bf16* arow = dzT + (int64_t)(ot * 32 + r) * bmax + 8 * half;
+  const __bf16* brow = ht + (int64_t)(it * 32 + r) * bmax + 8 * half;
+  int64_t kb = b0;
+  // four k-steps' fragments are loaded before their products, so four L2
+  // round trips overlap; the accumulation order is unchanged
+  for (; kb + 64 <= b1; kb += 64) {
+    bf16x8 aw[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      aw[u] = *reinterpret_cast<const bf16x8*>(arow + kb + 16 * u);
+      bv[u] = *reinterpret_cast<const bf16x8*>(brow + kb + 16 * u);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = mfma(aw[u], bv[u], acc);
   }
+  for (; kb < b1; kb += 16) acc = mfma(*reinterpret_cast<const bf16x8*>(arow + kb), *reinterpret_cast<const bf16x8*>(brow + kb), acc);
   float* ps = part + (int64_t)s * NP;
   const int i = it * 32 + r;
 #pragma unroll
@@ -701,7 +719,7 @@ kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batc
   auto zl = [&](int l) { return w.z + (int64_t)l * bmax * HID; };
   const dim3 gdx((unsigned)(b / RAYS));
   // layer 4
-  hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(1 * 8, SPLITS), dim3(64), 0, strm, w.dz4T, 32, 4, ht(4), 256, 256, bmax,
+  hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(1 * 8 * SPLITS), dim3(64), 0, strm, w.dz4T, 32, 4, ht(4), 256, 256, bmax,
                      (int64_t)b, w.part, h_OFF_W[4], h_OFF_B[4]);
   hipLaunchKernelGGL(k_mlp_bwd_dx, gdx, dim3(64), 0, strm, wbt + OFF_WBT[4], 32, w.dz4, zl(3), w.dz_a, w.dzT_a, bmax);
   // layers 3, 2, 1
@@ -710,14 +728,14 @@ kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batc
   __bf16* nxt = w.dz_b;
   __bf16* nxtT = w.dzT_b;
   for (int l = 3; l >= 1; --l) {
-    hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(8 * 8, SPLITS), dim3(64), 0, strm, curT, 256, 256, ht(l), 256, 256, bmax,
+    hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(8 * 8 * SPLITS), dim3(64), 0, strm, curT, 256, 256, ht(l), 256, 256, bmax,
                        (int64_t)b, w.part, h_OFF_W[l], h_OFF_B[l]);
     hipLaunchKernelGGL(k_mlp_bwd_dx, gdx, dim3(64), 0, strm, wbt + OFF_WBT[l], 256, cur, zl(l - 1), nxt, nxtT, bmax);
     std::swap(cur, nxt);
     std::swap(curT, nxtT);
   }
   // layer 0 (inputs padded to one 32-row tile)
-  hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(8 * 1, SPLITS), dim3(64), 0, strm, curT, 256, 256, ht(0), 32, 4, bmax,
+  hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(8 * 1 * SPLITS), dim3(64), 0, strm, curT, 256, 256, ht(0), 32, 4, bmax,
                      (int64_t)b, w.part, h_OFF_W[0], h_OFF_B[0]);
   KH_HIP(ctx, hipGetLastError());
   return KH_OK;
