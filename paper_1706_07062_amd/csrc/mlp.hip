@@ -3,13 +3,14 @@
 // Every product is written as D^T = W X^T: the weight tile is the MFMA A
 // operand (32 output features x 16 inputs, read straight from L2 as 16-byte
 // rows of the [out][in] BF16 copy) and the activations are the B operand
-// (16 inputs x 32 rays, read as 16-byte rows of a per-wave LDS tile
-// [ray][feature]).  The 32x32 accumulator then holds, per lane, four
+// (16 inputs x 32 rays).  The 32x32 accumulator then holds, per lane, four
 // consecutive output features of one ray, so bias, SiLU and the BF16 store of
-// the next activation row are one 8-byte write.  One wave owns 32 rays and
-// carries them through all five layers without leaving the CU.  (Training
-// keeps the activations in that LDS tile; inference, k_mlp_fwd_reg, keeps
-// them in registers and stages only weights through LDS.)
+// the next activation row are one 8-byte write.  Inference (k_mlp_fwd_reg):
+// one wave carries 32 rays through all five layers with its activations in
+// registers and the weights staged through LDS.  Training (k_mlp_fwd_train,
+// k_mlp_bwd_dx): batches are a few thousand rays, so four waves share a tile
+// of 32 rays and split each layer's outputs; the forward keeps the tile's
+// activations in LDS rows [ray][feature].
 //
 // MFMA operand layout used (v_mfma_f32_32x32x16_bf16, 64 lanes):
 //   A[i][k]: lane l holds i = l % 32, k = 8 (l / 32) + j, j = 0..7
@@ -87,15 +88,15 @@ __device__ inline f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c)
 struct FwdArgs {
   const float* params;
   const __bf16* wb;
-  const float* x;  // raw features [m][4] (modes 0 and 2)
+  const float* x;  // raw features [m][4] (forward and training)
   int64_t m;
   kh_camera cam;   // mode 1
-  float* y;        // raw outputs [m][4] (modes 0, 2) or decoded image (mode 1)
+  float* y;        // raw outputs [m][4], or the decoded image (camera mode)
   float tau;
   int32_t* fb_ids;
   int32_t* fb_count;
-  float* z;    // mode 2: pre-activations [4][bmax][256]
-  __bf16* ht;  // mode 2: HT_0 [32][bmax], then HT_1..HT_4 [256][bmax]
+  float* z;    // training: pre-activations [4][bmax][256]
+  __bf16* ht;  // training: HT_0 [32][bmax], then HT_1..HT_4 [256][bmax]
   int64_t bmax;
 };
 
@@ -103,138 +104,6 @@ __host__ __device__ inline __bf16* ht_layer(__bf16* ht, int l, int64_t bmax) {
   return l == 0 ? ht : ht + (int64_t)HT0_ROWS * bmax + (int64_t)(l - 1) * HID * bmax;
 }
 
-// Bias, SiLU and the stores of one hidden layer's accumulators.
-template <int MODE>
-__device__ inline void store_hidden(const FwdArgs& A, int l, const f32x16 (&acc)[8], __bf16* act, int r, int half,
-                                    int64_t ray, bool valid) {
-  const float* bias = A.params + OFF_B[l];
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int m0 = t * 32 + 8 * g + 4 * half;
-      const f32x4 b = *reinterpret_cast<const f32x4*>(bias + m0);
-      f32x4 zz;
-      bf16x4 hv;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        zz[q] = acc[t][4 * g + q] + b[q];
-        hv[q] = (__bf16)silu(zz[q]);
-      }
-      *reinterpret_cast<bf16x4*>(act + r * LDA + m0) = hv;
-      if (MODE == 2 && valid) {
-        *reinterpret_cast<f32x4*>(A.z + ((int64_t)l * A.bmax + ray) * HID + m0) = zz;
-        __bf16* ht = ht_layer(A.ht, l + 1, A.bmax);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ht[(int64_t)(m0 + q) * A.bmax + ray] = hv[q];
-      }
-    }
-  }
-}
-
-// MODE 0: raw outputs for raw features; 1: decoded camera image + fallback
-// list; 2: training forward (raw outputs, pre-activations and transposed
-// activations saved).
-template <int MODE>
-__global__ void __launch_bounds__(64) k_mlp_fwd(FwdArgs A) {
-  __shared__ __attribute__((aligned(16))) __bf16 act[RAYS * LDA];
-  const int lane = threadIdx.x, r = lane & 31, half = lane >> 5;
-  const int64_t ray = (int64_t)blockIdx.x * RAYS + r;
-  const bool valid = ray < A.m;
-
-  float f[4] = {0.f, 0.f, 0.f, 0.f};
-  if (valid) {
-    if (MODE == 1) {
-      const int64_t row = ray / A.cam.width, col = ray % A.cam.width;
-      const float al = (float)(A.cam.alpha_min + (col + 0.5) * (A.cam.alpha_max - A.cam.alpha_min) / A.cam.width);
-      const float be = (float)(A.cam.beta_min + (row + 0.5) * (A.cam.beta_max - A.cam.beta_min) / A.cam.height);
-      norm_features(al, be, (float)A.cam.a, (float)A.cam.incl, f);
-    } else {
-      const f32x4 xv = *reinterpret_cast<const f32x4*>(A.x + ray * 4);
-      norm_features(xv[0], xv[1], xv[2], xv[3], f);
-    }
-  }
-  // layer 0 (K = 4 padded to 16): B operand = features, rows 8 * half + j
-  bf16x8 bx;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) bx[j] = (half == 0 && j < 4) ? (__bf16)f[j] : (__bf16)0.0f;
-  if (MODE == 2 && valid) {
-    __bf16* ht0 = ht_layer(A.ht, 0, A.bmax);
-#pragma unroll
-    for (int j = 0; j < 16; ++j)
-      ht0[(int64_t)(16 * half + j) * A.bmax + ray] = (half == 0 && j < 4) ? (__bf16)f[j & 3] : (__bf16)0.0f;
-  }
-  f32x16 acc[8];
-  const f32x16 zero = {};
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[0] + (t * 32 + r) * KPAD[0] + 8 * half);
-    acc[t] = mfma(aw, bx, zero);
-  }
-  store_hidden<MODE>(A, 0, acc, act, r, half, ray, valid);
-
-  // hidden layers 1..3 (256 -> 256)
-  for (int l = 1; l < 4; ++l) {
-    wave_sync();
-    const __bf16* w = A.wb + (l == 1 ? OFF_WB[1] : l == 2 ? OFF_WB[2] : OFF_WB[3]);
-#pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] = zero;
-    for (int ks = 0; ks < HID / 16; ++ks) {
-      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(act + r * LDA + ks * 16 + 8 * half);
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const bf16x8 aw = *reinterpret_cast<const bf16x8*>(w + (t * 32 + r) * HID + ks * 16 + 8 * half);
-        acc[t] = mfma(aw, bv, acc[t]);
-      }
-    }
-    wave_sync();
-    store_hidden<MODE>(A, l, acc, act, r, half, ray, valid);
-  }
-
-  // output layer (256 -> 4, padded to 32 rows)
-  wave_sync();
-  f32x16 o = zero;
-  for (int ks = 0; ks < HID / 16; ++ks) {
-    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(act + r * LDA + ks * 16 + 8 * half);
-    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + r * HID + ks * 16 + 8 * half);
-    o = mfma(aw, bv, o);
-  }
-  // outputs 0..3 of ray r sit in elements 0..3 of lane r (half 0)
-  bool unsure = false;
-  if (half == 0 && valid) {
-    const float* b4 = A.params + OFF_B[4];
-    f32x4 y;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) y[q] = o[q] + b4[q];
-    if (MODE == 1) {
-      const float p = sigmoidf(y[3]);
-      f32x4 d;
-      d[0] = __expf(2.0f * y[0] + 2.0f);
-      d[1] = 3.14159265358979f * y[1];
-      d[2] = 0.3f * y[2] + 0.8f;
-      d[3] = p;
-      *reinterpret_cast<f32x4*>(A.y + ray * 4) = d;
-      unsure = p > A.tau && p < 1.0f - A.tau;
-    } else {
-      *reinterpret_cast<f32x4*>(A.y + ray * 4) = y;
-    }
-  }
-  if (MODE == 1) {
-    // wave-aggregated append of the uncertain pixels
-    const unsigned long long mask = __ballot(unsure);
-    if (mask) {
-      const int leader = __ffsll((long long)mask) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(A.fb_count, __popcll(mask));
-      base = __shfl(base, leader);
-      if (unsure) {
-        const unsigned rank =
-            __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-        A.fb_ids[base + rank] = (int32_t)ray;
-      }
-    }
-  }
-}
 
 // Inference forward with the activations kept in registers.  After a layer's
 // epilogue each lane holds, for its ray, the features of rows
@@ -419,6 +288,103 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
   }
 }
 
+// Training forward for batches of a few thousand rays: a block of four waves
+// carries one tile of 32 rays and each wave computes 64 of a layer's 256
+// outputs (two accumulator tiles), so a batch of b rays keeps b / 8 waves
+// busy instead of b / 32.  The tile's activations live in LDS ([ray][feature]
+// rows, double-buffered: one barrier per layer).  Saves what the backward
+// pass needs: pre-activations z and the transposed BF16 activations.
+__global__ void __launch_bounds__(256) k_mlp_fwd_train(FwdArgs A) {
+  __shared__ __attribute__((aligned(16))) __bf16 act[2][RAYS * LDA];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = lane & 31, half = lane >> 5;
+  const int64_t ray = (int64_t)blockIdx.x * RAYS + r;
+  const bool valid = ray < A.m;
+
+  float f[4] = {0.f, 0.f, 0.f, 0.f};
+  if (valid) {
+    const f32x4 xv = *reinterpret_cast<const f32x4*>(A.x + ray * 4);
+    norm_features(xv[0], xv[1], xv[2], xv[3], f);
+  }
+  bf16x8 bx;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) bx[j] = (half == 0 && j < 4) ? (__bf16)f[j] : (__bf16)0.0f;
+  if (w == 0 && valid) {
+    __bf16* ht0 = ht_layer(A.ht, 0, A.bmax);
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      ht0[(int64_t)(16 * half + j) * A.bmax + ray] = (half == 0 && j < 4) ? (__bf16)f[j & 3] : (__bf16)0.0f;
+  }
+  const f32x16 zero = {};
+  f32x16 acc[2];
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt) {
+    const int t = 2 * w + tt;
+    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[0] + (t * 32 + r) * KPAD[0] + 8 * half);
+    acc[tt] = mfma(aw, bx, zero);
+  }
+  for (int l = 0; l < 4; ++l) {
+    if (l > 0) {
+      const __bf16* in = act[(l - 1) & 1];
+      const __bf16* wl = A.wb + (l == 1 ? OFF_WB[1] : l == 2 ? OFF_WB[2] : OFF_WB[3]);
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt) acc[tt] = zero;
+      for (int ks = 0; ks < HID / 16; ++ks) {
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(in + r * LDA + ks * 16 + 8 * half);
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+          const int t = 2 * w + tt;
+          const bf16x8 aw = *reinterpret_cast<const bf16x8*>(wl + (t * 32 + r) * HID + ks * 16 + 8 * half);
+          acc[tt] = mfma(aw, bv, acc[tt]);
+        }
+      }
+    }
+    // bias, SiLU, the next activation rows and the saved tensors of this wave's outputs
+    const float* bias = A.params + OFF_B[l];
+    __bf16* out = act[l & 1];
+    __bf16* ht = ht_layer(A.ht, l + 1, A.bmax);
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int m0 = (2 * w + tt) * 32 + 8 * g + 4 * half;
+        const f32x4 b = *reinterpret_cast<const f32x4*>(bias + m0);
+        f32x4 zz;
+        bf16x4 hv;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          zz[q] = acc[tt][4 * g + q] + b[q];
+          hv[q] = (__bf16)silu(zz[q]);
+        }
+        *reinterpret_cast<bf16x4*>(out + r * LDA + m0) = hv;
+        if (valid) {
+          *reinterpret_cast<f32x4*>(A.z + ((int64_t)l * A.bmax + ray) * HID + m0) = zz;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) ht[(int64_t)(m0 + q) * A.bmax + ray] = hv[q];
+        }
+      }
+    }
+    __syncthreads();  // the layer's activation rows are complete
+  }
+
+  // output layer (256 -> 4, padded to 32 rows), one wave
+  if (w == 0) {
+    const __bf16* in = act[1];
+    f32x16 o = zero;
+    for (int ks = 0; ks < HID / 16; ++ks) {
+      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(in + r * LDA + ks * 16 + 8 * half);
+      const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + r * HID + ks * 16 + 8 * half);
+      o = mfma(aw, bv, o);
+    }
+    if (half == 0 && valid) {
+      const float* b4 = A.params + OFF_B[4];
+      f32x4 y;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) y[q] = o[q] + b4[q];
+      *reinterpret_cast<f32x4*>(A.y + ray * 4) = y;
+    }
+  }
+}
+
 // Loss and its gradient with respect to the raw outputs; dz [bmax][32] and
 // dzT [32][bmax] (BF16, columns / rows 4..31 zero).
 __global__ void k_mlp_loss(const float* y, const float* t, const uint8_t* mask, int64_t b, __bf16* dz, __bf16* dzT,
@@ -457,32 +423,34 @@ __global__ void k_mlp_loss(const float* y, const float* t, const uint8_t* mask, 
 
 // Gradient with respect to a layer's input, times SiLU' of the layer below:
 // dz_out[ray][k] = (sum_o dz[ray][o] W[o][k]) * silu'(zprev[ray][k]).
-__global__ void __launch_bounds__(64) k_mlp_bwd_dx(const __bf16* wbt, int opad, const __bf16* dz, const float* zprev,
-                                                    __bf16* dz_out, __bf16* dzT_out, int64_t bmax) {
-  const int lane = threadIdx.x, r = lane & 31, half = lane >> 5;
+__global__ void __launch_bounds__(256) k_mlp_bwd_dx(const __bf16* wbt, int opad, const __bf16* dz, const float* zprev,
+                                                     __bf16* dz_out, __bf16* dzT_out, int64_t bmax) {
+  // one tile of 32 rays per block; wave w computes input features 64 w .. 64 w + 63
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = lane & 31, half = lane >> 5;
   const int64_t ray = (int64_t)blockIdx.x * RAYS + r;
-  f32x16 acc[8];
+  f32x16 acc[2];
   const f32x16 zero = {};
 #pragma unroll
-  for (int t = 0; t < 8; ++t) acc[t] = zero;
+  for (int tt = 0; tt < 2; ++tt) acc[tt] = zero;
 #pragma unroll 4
   for (int os = 0; os < opad / 16; ++os) {
     const bf16x8 bv = *reinterpret_cast<const bf16x8*>(dz + ray * opad + os * 16 + 8 * half);
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int tt = 0; tt < 2; ++tt) {
+      const int t = 2 * w + tt;
       const bf16x8 aw = *reinterpret_cast<const bf16x8*>(wbt + (t * 32 + r) * opad + os * 16 + 8 * half);
-      acc[t] = mfma(aw, bv, acc[t]);
+      acc[tt] = mfma(aw, bv, acc[tt]);
     }
   }
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
+  for (int tt = 0; tt < 2; ++tt) {
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      const int k0 = t * 32 + 8 * g + 4 * half;
+      const int k0 = (2 * w + tt) * 32 + 8 * g + 4 * half;
       const f32x4 zz = *reinterpret_cast<const f32x4*>(zprev + ray * HID + k0);
       bf16x4 dv;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) dv[q] = (__bf16)(acc[t][4 * g + q] * dsilu(zz[q]));
+      for (int q = 0; q < 4; ++q) dv[q] = (__bf16)(acc[tt][4 * g + q] * dsilu(zz[q]));
       *reinterpret_cast<bf16x4*>(dz_out + ray * HID + k0) = dv;
 #pragma unroll
       for (int q = 0; q < 4; ++q) dzT_out[(int64_t)(k0 + q) * bmax + ray] = dv[q];
@@ -532,10 +500,17 @@ __global__ void __launch_bounds__(64) k_mlp_bwd_dw(const __bf16* dzT, int opad, 
     if (o < nout && i < nin) ps[off_w + o * nin + i] = acc[e];
   }
   if (it == 0) {
+    // bias gradient: each half of the wave sums half of the split in order,
+    // eight values per 16-byte load (per is a multiple of 16)
     const int o = ot * 32 + r;
     const int64_t mid = b0 + per / 2;
+    const __bf16* row = dzT + (int64_t)o * bmax;
     float sb = 0.0f;
-    for (int64_t kb = half ? mid : b0; kb < (half ? b1 : mid); ++kb) sb += (float)dzT[(int64_t)o * bmax + kb];
+    for (int64_t kb = half ? mid : b0; kb < (half ? b1 : mid); kb += 8) {
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(row + kb);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sb += (float)v[j];
+    }
     sb += __shfl_down(sb, 32);
     if (half == 0 && o < nout) ps[off_b + o] = sb;
   }
@@ -711,7 +686,7 @@ kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batc
   A.z = w.z;
   A.ht = w.ht;
   A.bmax = bmax;
-  hipLaunchKernelGGL(k_mlp_fwd<2>, dim3((unsigned)(b / RAYS)), dim3(64), 0, strm, A);
+  hipLaunchKernelGGL(k_mlp_fwd_train, dim3((unsigned)(b / RAYS)), dim3(256), 0, strm, A);
   hipLaunchKernelGGL(k_mlp_loss, dim3((unsigned)(b / 256)), dim3(256), 0, strm, w.y, t, mask, (int64_t)b, w.dz4,
                      w.dz4T, bmax, loss);
   const __bf16* wbt = reinterpret_cast<const __bf16*>(net->wbt);
@@ -721,7 +696,7 @@ kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batc
   // layer 4
   hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(1 * 8 * SPLITS), dim3(64), 0, strm, w.dz4T, 32, 4, ht(4), 256, 256, bmax,
                      (int64_t)b, w.part, h_OFF_W[4], h_OFF_B[4]);
-  hipLaunchKernelGGL(k_mlp_bwd_dx, gdx, dim3(64), 0, strm, wbt + OFF_WBT[4], 32, w.dz4, zl(3), w.dz_a, w.dzT_a, bmax);
+  hipLaunchKernelGGL(k_mlp_bwd_dx, gdx, dim3(256), 0, strm, wbt + OFF_WBT[4], 32, w.dz4, zl(3), w.dz_a, w.dzT_a, bmax);
   // layers 3, 2, 1
   __bf16* cur = w.dz_a;
   __bf16* curT = w.dzT_a;
@@ -730,7 +705,7 @@ kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batc
   for (int l = 3; l >= 1; --l) {
     hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(8 * 8 * SPLITS), dim3(64), 0, strm, curT, 256, 256, ht(l), 256, 256, bmax,
                        (int64_t)b, w.part, h_OFF_W[l], h_OFF_B[l]);
-    hipLaunchKernelGGL(k_mlp_bwd_dx, gdx, dim3(64), 0, strm, wbt + OFF_WBT[l], 256, cur, zl(l - 1), nxt, nxtT, bmax);
+    hipLaunchKernelGGL(k_mlp_bwd_dx, gdx, dim3(256), 0, strm, wbt + OFF_WBT[l], 256, cur, zl(l - 1), nxt, nxtT, bmax);
     std::swap(cur, nxt);
     std::swap(curT, nxtT);
   }
