@@ -479,17 +479,17 @@ __global__ void __launch_bounds__(64) k_mlp_bwd_dw(const __bf16* dzT, int opad, 
   const __bf16* arow = dzT + (int64_t)(ot * 32 + r) * bmax + 8 * half;
   const __bf16* brow = ht + (int64_t)(it * 32 + r) * bmax + 8 * half;
   int64_t kb = b0;
-  // four k-steps' fragments are loaded before their products, so four L2
+  // eight k-steps' fragments are loaded before their products, so eight L2
   // round trips overlap; the accumulation order is unchanged
-  for (; kb + 64 <= b1; kb += 64) {
-    bf16x8 aw[4], bv[4];
+  for (; kb + 128 <= b1; kb += 128) {
+    bf16x8 aw[8], bv[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       aw[u] = *reinterpret_cast<const bf16x8*>(arow + kb + 16 * u);
       bv[u] = *reinterpret_cast<const bf16x8*>(brow + kb + 16 * u);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = mfma(aw[u], bv[u], acc);
+    for (int u = 0; u < 8; ++u) acc = mfma(aw[u], bv[u], acc);
   }
   for (; kb < b1; kb += 16) acc = mfma(*reinterpret_cast<const bf16x8*>(arow + kb), *reinterpret_cast<const bf16x8*>(brow + kb), acc);
   float* ps = part + (int64_t)s * NP;
@@ -506,6 +506,7 @@ __global__ void __launch_bounds__(64) k_mlp_bwd_dw(const __bf16* dzT, int opad, 
     const int64_t mid = b0 + per / 2;
     const __bf16* row = dzT + (int64_t)o * bmax;
     float sb = 0.0f;
+#pragma unroll 4
     for (int64_t kb = half ? mid : b0; kb < (half ? b1 : mid); kb += 8) {
       const bf16x8 v = *reinterpret_cast<const bf16x8*>(row + kb);
 #pragma unroll
