@@ -288,6 +288,137 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
   }
 }
 
+// Inference forward as a plain GEMM tiling: a block of four waves carries 128
+// rays; wave w computes outputs 64 w .. 64 w + 63 of every layer for all 128
+// rays (2 x 4 accumulator tiles).  Its weight fragments (its 64 rows) come from
+// L2, one k-step ahead; the activations of the 128 rays sit in LDS rows
+// [ray][feature], read by every wave and rewritten after each layer between
+// two barriers.
+template <int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_mlp_fwd_split(FwdArgs A) {
+  __shared__ __attribute__((aligned(16))) __bf16 act[4 * RAYS * LDA];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = lane & 31, half = lane >> 5;
+  const int64_t base = (int64_t)blockIdx.x * (4 * RAYS);
+
+  const f32x16 zero = {};
+  f32x16 acc[2][4];
+  // layer 0 (K = 4 padded to 16): the B operand of ray tile n is ray base + 32 n + r
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    const int64_t ray = base + 32 * n + r;
+    float f[4] = {0.f, 0.f, 0.f, 0.f};
+    if (ray < A.m) {
+      if (MODE == 1) {
+        const int64_t row = ray / A.cam.width, col = ray % A.cam.width;
+        const float al = (float)(A.cam.alpha_min + (col + 0.5) * (A.cam.alpha_max - A.cam.alpha_min) / A.cam.width);
+        const float be = (float)(A.cam.beta_min + (row + 0.5) * (A.cam.beta_max - A.cam.beta_min) / A.cam.height);
+        norm_features(al, be, (float)A.cam.a, (float)A.cam.incl, f);
+      } else {
+        const f32x4 xv = *reinterpret_cast<const f32x4*>(A.x + ray * 4);
+        norm_features(xv[0], xv[1], xv[2], xv[3], f);
+      }
+    }
+    bf16x8 bx;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bx[j] = (half == 0 && j < 4) ? (__bf16)f[j] : (__bf16)0.0f;
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+      const bf16x8 aw =
+          *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[0] + ((2 * w + tt) * 32 + r) * KPAD[0] + 8 * half);
+      acc[tt][n] = mfma(aw, bx, zero);
+    }
+  }
+  for (int l = 0; l < 4; ++l) {
+    if (l > 0) {
+      const __bf16* wl = A.wb + (l == 1 ? OFF_WB[1] : l == 2 ? OFF_WB[2] : OFF_WB[3]);
+      const __bf16* arow0 = wl + ((2 * w) * 32 + r) * HID + 8 * half;
+      const __bf16* arow1 = arow0 + 32 * HID;
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[tt][n] = zero;
+      bf16x8 a0 = *reinterpret_cast<const bf16x8*>(arow0);
+      bf16x8 a1 = *reinterpret_cast<const bf16x8*>(arow1);
+      for (int ks = 0; ks < HID / 16; ++ks) {
+        bf16x8 n0 = a0, n1 = a1;
+        if (ks + 1 < HID / 16) {
+          n0 = *reinterpret_cast<const bf16x8*>(arow0 + (ks + 1) * 16);
+          n1 = *reinterpret_cast<const bf16x8*>(arow1 + (ks + 1) * 16);
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(act + (32 * n + r) * LDA + ks * 16 + 8 * half);
+          acc[0][n] = mfma(a0, bv, acc[0][n]);
+          acc[1][n] = mfma(a1, bv, acc[1][n]);
+        }
+        a0 = n0;
+        a1 = n1;
+      }
+      __syncthreads();  // every wave is done reading this layer's input rows
+    }
+    const float* bias = A.params + (l == 0 ? OFF_B[0] : l == 1 ? OFF_B[1] : l == 2 ? OFF_B[2] : OFF_B[3]);
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int m0 = (2 * w + tt) * 32 + 8 * g + 4 * half;
+        const f32x4 b = *reinterpret_cast<const f32x4*>(bias + m0);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          bf16x4 hv;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) hv[q] = (__bf16)silu(acc[tt][n][4 * g + q] + b[q]);
+          *reinterpret_cast<bf16x4*>(act + (32 * n + r) * LDA + m0) = hv;
+        }
+      }
+    }
+    __syncthreads();  // the next layer's input rows are complete
+  }
+
+  // output layer (256 -> 4, padded to 32 rows): wave w takes ray tile w
+  const int64_t ray = base + 32 * w + r;
+  const bool valid = ray < A.m;
+  f32x16 o = zero;
+  for (int ks = 0; ks < HID / 16; ++ks) {
+    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(act + (32 * w + r) * LDA + ks * 16 + 8 * half);
+    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + r * HID + ks * 16 + 8 * half);
+    o = mfma(aw, bv, o);
+  }
+  bool unsure = false;
+  if (half == 0 && valid) {
+    const float* b4 = A.params + OFF_B[4];
+    f32x4 y;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) y[q] = o[q] + b4[q];
+    if (MODE == 1) {
+      const float pc = sigmoidf(y[3]);
+      f32x4 d;
+      d[0] = __expf(2.0f * y[0] + 2.0f);
+      d[1] = 3.14159265358979f * y[1];
+      d[2] = 0.3f * y[2] + 0.8f;
+      d[3] = pc;
+      *reinterpret_cast<f32x4*>(A.y + ray * 4) = d;
+      unsure = pc > A.tau && pc < 1.0f - A.tau;
+    } else {
+      *reinterpret_cast<f32x4*>(A.y + ray * 4) = y;
+    }
+  }
+  if (MODE == 1) {
+    const unsigned long long mask = __ballot(unsure);
+    if (mask) {
+      const int leader = __ffsll((long long)mask) - 1;
+      int slot = 0;
+      if (lane == leader) slot = atomicAdd(A.fb_count, __popcll(mask));
+      slot = __shfl(slot, leader);
+      if (unsure) {
+        const unsigned rank =
+            __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+        A.fb_ids[slot + rank] = (int32_t)ray;
+      }
+    }
+  }
+}
+
 // Training forward for batches of a few thousand rays: a block of four waves
 // carries one tile of 32 rays and each wave computes 64 of a layer's 256
 // outputs (two accumulator tiles), so a batch of b rays keeps b / 8 waves
@@ -764,7 +895,7 @@ kh_status kh_mlp_forward(kh_ctx* ctx, const kh_mlp* net, const float* x, float* 
   A.x = x;
   A.m = m;
   A.y = y;
-  hipLaunchKernelGGL(k_mlp_fwd_reg<0>, dim3((unsigned)((m + 4 * RAYS - 1) / (4 * RAYS))), dim3(256), 0,
+  hipLaunchKernelGGL(k_mlp_fwd_split<0>, dim3((unsigned)((m + 4 * RAYS - 1) / (4 * RAYS))), dim3(256), 0,
                      (hipStream_t)stream, A);
   KH_HIP(ctx, hipGetLastError());
   return KH_OK;
@@ -797,7 +928,7 @@ kh_status kh_mlp_image(kh_ctx* ctx, const kh_mlp* net, const kh_camera* cam, flo
   A.tau = tau;
   A.fb_ids = fallback_ids;
   A.fb_count = fallback_count;
-  hipLaunchKernelGGL(k_mlp_fwd_reg<1>, dim3((unsigned)((m + 4 * RAYS - 1) / (4 * RAYS))), dim3(256), 0, strm, A);
+  hipLaunchKernelGGL(k_mlp_fwd_split<1>, dim3((unsigned)((m + 4 * RAYS - 1) / (4 * RAYS))), dim3(256), 0, strm, A);
   KH_HIP(ctx, hipGetLastError());
   return KH_OK;
 }
