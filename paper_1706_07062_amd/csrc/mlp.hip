@@ -5,12 +5,11 @@
 // rows of the [out][in] BF16 copy) and the activations are the B operand
 // (16 inputs x 32 rays).  The 32x32 accumulator then holds, per lane, four
 // consecutive output features of one ray, so bias, SiLU and the BF16 store of
-// the next activation row are one 8-byte write.  Inference (k_mlp_fwd_reg):
-// one wave carries 32 rays through all five layers with its activations in
-// registers and the weights staged through LDS.  Training (k_mlp_fwd_train,
-// k_mlp_bwd_dx): batches are a few thousand rays, so four waves share a tile
-// of 32 rays and split each layer's outputs; the forward keeps the tile's
-// activations in LDS rows [ray][feature].
+// the next activation row are one 8-byte write.  In every kernel the waves of
+// a block split each layer's 256 outputs and share the block's activations in
+// LDS rows [ray][feature]: inference (k_mlp_fwd_split) with 128 rays per
+// block, training (k_mlp_fwd_train, k_mlp_bwd_dx) with 32, because a training
+// batch is only a few thousand rays.
 //
 // MFMA operand layout used (v_mfma_f32_32x32x16_bf16, 64 lanes):
 //   A[i][k]: lane l holds i = l % 32, k = 8 (l / 32) + j, j = 0..7
@@ -104,189 +103,6 @@ __host__ __device__ inline __bf16* ht_layer(__bf16* ht, int l, int64_t bmax) {
   return l == 0 ? ht : ht + (int64_t)HT0_ROWS * bmax + (int64_t)(l - 1) * HID * bmax;
 }
 
-
-// Inference forward with the activations kept in registers.  After a layer's
-// epilogue each lane holds, for its ray, the features of rows
-// 32 t + 8 g + 4 h + q (h = l / 32); the next layer's B fragment for k-step
-// ks = 2 t + s needs rows 32 t + 16 s + 8 h + j, j = 0..7, i.e. group
-// g = 2 s + h, four rows from each half of the wave.  One v_permlane32_swap
-// per 32-bit pair exchanges the group the other half needs, so activations
-// never go through LDS.  LDS then holds only the hidden layers' weights,
-// staged in slabs of 32 inputs x 256 outputs shared by the block's four waves:
-// a ring of three slots, one barrier per slab, each slab loaded from L2 into
-// registers three iterations before it is read.  The three hidden layers
-// are one stream of 24 slabs, so the stream runs on across layer boundaries.
-constexpr int SLAB_K = 32;            // inputs per slab (two MFMA k-steps)
-constexpr int SROW = SLAB_K + 8;      // slab row stride (BF16): 80 bytes
-constexpr int NSLABS = 3 * HID / SLAB_K;
-constexpr int NSLOT = 3;              // LDS slots of the slab ring
-
-__device__ inline const __bf16* slab_src(const __bf16* wb, int g, int row) {
-  const int l = 1 + g / (HID / SLAB_K), s = g % (HID / SLAB_K);
-  return wb + (l == 1 ? OFF_WB[1] : l == 2 ? OFF_WB[2] : OFF_WB[3]) + row * HID + s * SLAB_K;
-}
-
-// Bias and SiLU of one layer's accumulators, rearranged into the next layer's
-// 16 B fragments (register-resident).
-__device__ inline void acc_to_act(const float* bias, const f32x16 (&acc)[8], int half, bf16x8 (&act)[16]) {
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-      unsigned u[2][2];
-#pragma unroll
-      for (int gg = 0; gg < 2; ++gg) {
-        const int g = 2 * s + gg;
-        const int m0 = t * 32 + 8 * g + 4 * half;
-        const f32x4 b = *reinterpret_cast<const f32x4*>(bias + m0);
-        bf16x4 hv;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) hv[q] = (__bf16)silu(acc[t][4 * g + q] + b[q]);
-        const u32x2 pk = __builtin_bit_cast(u32x2, hv);
-        u[gg][0] = pk[0];
-        u[gg][1] = pk[1];
-      }
-      // lower half keeps group 2 s and takes the upper half's; the upper half
-      // keeps group 2 s + 1 and takes the lower half's
-#pragma unroll
-      for (int d = 0; d < 2; ++d) {
-        const auto pr = __builtin_amdgcn_permlane32_swap(u[0][d], u[1][d], false, false);
-        u[0][d] = pr[0];
-        u[1][d] = pr[1];
-      }
-      typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-      const u32x4 v = {u[0][0], u[0][1], u[1][0], u[1][1]};
-      act[2 * t + s] = __builtin_bit_cast(bf16x8, v);
-    }
-  }
-}
-
-template <int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_mlp_fwd_reg(FwdArgs A) {
-  __shared__ __attribute__((aligned(16))) __bf16 wsl[NSLOT][HID * SROW];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = lane & 31, half = lane >> 5;
-  const int64_t ray = (int64_t)blockIdx.x * (4 * RAYS) + w * RAYS + r;
-  const bool valid = ray < A.m;
-
-  // slabs 0 and 1 of the weight stream into slots 0 and 1; slab 2 in flight
-  bf16x8 p[4];
-#pragma unroll
-  for (int g = 0; g < 3; ++g) {
-    const __bf16* src = slab_src(A.wb, g, tid);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) p[c] = *reinterpret_cast<const bf16x8*>(src + 8 * c);
-    if (g < 2) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) *reinterpret_cast<bf16x8*>(&wsl[g][tid * SROW + 8 * c]) = p[c];
-    }
-  }
-
-  float f[4] = {0.f, 0.f, 0.f, 0.f};
-  if (valid) {
-    if (MODE == 1) {
-      const int64_t row = ray / A.cam.width, col = ray % A.cam.width;
-      const float al = (float)(A.cam.alpha_min + (col + 0.5) * (A.cam.alpha_max - A.cam.alpha_min) / A.cam.width);
-      const float be = (float)(A.cam.beta_min + (row + 0.5) * (A.cam.beta_max - A.cam.beta_min) / A.cam.height);
-      norm_features(al, be, (float)A.cam.a, (float)A.cam.incl, f);
-    } else {
-      const f32x4 xv = *reinterpret_cast<const f32x4*>(A.x + ray * 4);
-      norm_features(xv[0], xv[1], xv[2], xv[3], f);
-    }
-  }
-  bf16x8 bx;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) bx[j] = (half == 0 && j < 4) ? (__bf16)f[j] : (__bf16)0.0f;
-  f32x16 acc[8];
-  const f32x16 zero = {};
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[0] + (t * 32 + r) * KPAD[0] + 8 * half);
-    acc[t] = mfma(aw, bx, zero);
-  }
-  bf16x8 act[16];
-  acc_to_act(A.params + OFF_B[0], acc, half, act);
-  __syncthreads();  // slots 0 and 1 are complete
-
-  // Iteration g first stores slab g + 2 (loaded during iteration g - 1) into
-  // slot (g + 2) % 3, last read in iteration g - 1, which every wave has
-  // finished once it is past the barrier that ends g - 1; then it starts the
-  // load of slab g + 3 and reads slab g from slot g % 3 (stored at the start of
-  // iteration g - 2 and published by the barrier that ended it).  A load thus
-  // has a whole iteration and a barrier to arrive.  The loop is unrolled within
-  // a layer so that act[] is indexed by constants and stays in registers.
-  for (int l = 1; l < 4; ++l) {
-#pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] = zero;
-#pragma unroll
-    for (int s = 0; s < HID / SLAB_K; ++s) {
-      const int g = (l - 1) * (HID / SLAB_K) + s;
-      if (g + 2 < NSLABS) {
-        __bf16* dst = wsl[(g + 2) % NSLOT];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) *reinterpret_cast<bf16x8*>(&dst[tid * SROW + 8 * c]) = p[c];
-      }
-      if (g + 3 < NSLABS) {
-        const __bf16* src = slab_src(A.wb, g + 3, tid);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) p[c] = *reinterpret_cast<const bf16x8*>(src + 8 * c);
-      }
-      const __bf16* slot = wsl[g % NSLOT];
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk) {
-        const bf16x8 bv = act[2 * s + kk];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const bf16x8 aw = *reinterpret_cast<const bf16x8*>(slot + (t * 32 + r) * SROW + 16 * kk + 8 * half);
-          acc[t] = mfma(aw, bv, acc[t]);
-        }
-      }
-      if (s == HID / SLAB_K - 1)
-        acc_to_act(A.params + (l == 1 ? OFF_B[1] : l == 2 ? OFF_B[2] : OFF_B[3]), acc, half, act);
-      __syncthreads();
-    }
-  }
-
-  f32x16 o = zero;
-#pragma unroll
-  for (int ks = 0; ks < HID / 16; ++ks) {
-    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + r * HID + ks * 16 + 8 * half);
-    o = mfma(aw, act[ks], o);
-  }
-  bool unsure = false;
-  if (half == 0 && valid) {
-    const float* b4 = A.params + OFF_B[4];
-    f32x4 y;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) y[q] = o[q] + b4[q];
-    if (MODE == 1) {
-      const float pc = sigmoidf(y[3]);
-      f32x4 d;
-      d[0] = __expf(2.0f * y[0] + 2.0f);
-      d[1] = 3.14159265358979f * y[1];
-      d[2] = 0.3f * y[2] + 0.8f;
-      d[3] = pc;
-      *reinterpret_cast<f32x4*>(A.y + ray * 4) = d;
-      unsure = pc > A.tau && pc < 1.0f - A.tau;
-    } else {
-      *reinterpret_cast<f32x4*>(A.y + ray * 4) = y;
-    }
-  }
-  if (MODE == 1) {
-    const unsigned long long mask = __ballot(unsure);
-    if (mask) {
-      const int leader = __ffsll((long long)mask) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(A.fb_count, __popcll(mask));
-      base = __shfl(base, leader);
-      if (unsure) {
-        const unsigned rank =
-            __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-        A.fb_ids[base + rank] = (int32_t)ray;
-      }
-    }
-  }
-}
 
 // Inference forward as a plain GEMM tiling: a block of four waves carries 128
 // rays; wave w computes outputs 64 w .. 64 w + 63 of every layer for all 128
