@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 
 POS_TOL = 1e-6
 ILL_TOL = 1e-7
-CHARTS = {K.RHS_FACTORED: "ks", K.RHS_BL: "bl"}
+CHARTS = {K.RHS_FACTORED: "ks", K.RHS_PAPER: "ks", K.RHS_BL: "bl"}
 
 
 def say(msg):
@@ -107,7 +107,7 @@ def test_pack_matches_oracle(ctx, form):
     assert err.max() < 1e-13
 
 
-@pytest.mark.parametrize("form", [K.RHS_FACTORED, K.RHS_BL])
+@pytest.mark.parametrize("form", [K.RHS_FACTORED, K.RHS_PAPER, K.RHS_BL])
 def test_rk4_fixed_parity_fp64(ctx, form):
     cam = _small_camera()
     chart = CHARTS[form]
