@@ -213,6 +213,11 @@ def test_fixed_argument_errors(ctx):
     rc = K.lib().kh_rk4_fixed(ctx.handle, ctypes.byref(good), host.data_ptr(), fs.status.data_ptr(),
                               fs.steps.data_ptr(), cam.n, None)
     assert rc == K.KH_EINVAL
+    # negative and oversized counts are refused from the size alone
+    for n_bad in (-1, 1 << 31):
+        rc = K.lib().kh_rk4_fixed(ctx.handle, ctypes.byref(good), fs.y.data_ptr(), fs.status.data_ptr(),
+                                  fs.steps.data_ptr(), n_bad, None)
+        assert rc == K.KH_EINVAL and b"2^31" in K.lib().kh_last_error(ctx.handle), n_bad
     # n = 0 is a no-op
     e = torch.zeros(0, dtype=torch.int32, device="cuda")
     ctx.kh_rk4_fixed(good, torch.zeros(0, dtype=torch.float64, device="cuda"), e, e)

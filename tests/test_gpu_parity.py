@@ -2,6 +2,8 @@
 same seeded inputs.  Positions must agree to 1e-6 relative with identical
 statuses on every ray the oracle does not flag as ill-conditioned
 (tests/parity_util.py states the policy)."""
+import ctypes as C
+
 import numpy as np
 import pytest
 import torch
@@ -322,6 +324,18 @@ def test_argument_errors(ctx):
     with pytest.raises(K.KerrHipError, match="device memory"):
         ctx.kh_integrate(K.kh_default_params(), st)
     st.c.h = saved
+    # empty and oversized states are refused from the size alone (no pointer is touched)
+    for n_bad in (0, -5, 1 << 31):
+        fake = K.kh_state.from_buffer_copy(st.c)
+        fake.n = n_bad
+        rc = K.lib().kh_integrate(ctx.handle, C.byref(K.kh_default_params()), C.byref(fake), None)
+        assert rc == K.KH_EINVAL, n_bad
+        assert b"state.n" in K.lib().kh_last_error(ctx.handle)
+    # unknown method / precision / form; the Boyer-Lindquist form is for the fixed-step kernel only
+    for field, val, msg in (("method", 9, "method"), ("precision", 7, "precision"), ("rhs_form", 5, "rhs_form"),
+                            ("rhs_form", K.RHS_BL, "rhs_form"), ("k_cross", 9, "k_cross")):
+        with pytest.raises(K.KerrHipError, match=msg):
+            ctx.kh_integrate(K.kh_default_params(**{field: val}), st)
 
 
 def test_tile_order_is_a_permutation_and_does_not_change_results(ctx):
