@@ -342,7 +342,8 @@ def batched_extra(ctx, K, W, torch):
 def particles_extra(ctx, K, W, torch):
     """2^20 time-like geodesics to t = 1e4 M: FP64 (rtol 1e-8) and FP32
     (rtol 1e-6), each with the affine parameter and in coordinate time,
-    constants-of-motion drift per particle."""
+    constants-of-motion drift per particle.  The states carry the
+    per-geodesic schedule (longest expected first)."""
     pw = W.particles()
     n = len(pw["a"])
     t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()  # noqa: E731
@@ -352,7 +353,7 @@ def particles_extra(ctx, K, W, torch):
     for name, prec, tol, method in (("fp64", K.P64, 1e-8, K.DOPRI5), ("fp32", K.P32, 1e-6, K.DOPRI5),
                                     ("fp64_coordinate_time", K.P64, 1e-8, K.DOPRI5_T),
                                     ("fp32_coordinate_time", K.P32, 1e-6, K.DOPRI5_T)):
-        st = K.State(n)
+        st = K.State(n, schedule="geodesics")
         p = K.kh_default_params(precision=prec, rtol=tol, atol=tol, t_end=1e4, r_escape=1e4, method=method)
         ctx.kh_init_geodesics(K.TIMELIKE, spin, x3, v3, st)
         torch.cuda.synchronize()
@@ -376,7 +377,7 @@ def particles_extra(ctx, K, W, torch):
     out["fp32_vs_fp64_position"] = dict(median=float(np.median(d)), p99=float(np.quantile(d, 0.99)))
     # dense output: the FP64 coordinate-time run again with states at 100 times
     t_out = np.linspace(100.0, 1e4, 100)
-    st = K.State(n, t_out=t_out)
+    st = K.State(n, t_out=t_out, schedule="geodesics")
     p = K.kh_default_params(method=K.DOPRI5_T, t_end=1e4, r_escape=1e4)
     ctx.kh_init_geodesics(K.TIMELIKE, spin, x3, v3, st)
     torch.cuda.synchronize()

@@ -111,6 +111,13 @@ typedef struct {
                             coordinate time k^0 is fixed by the entry energy as on exit.  kh_integrate writes
                             the targets in [t at entry, t at exit] (a target equal to the entry time gets the
                             entry state) and leaves every other entry untouched. */
+  int32_t *perm;    /* [n] or NULL: a per-geodesic schedule, which replaces `order` when set: position q of
+                       the work queue is geodesic perm[q].  The init calls write it longest-expected-first
+                       (see kh_init_geodesics); a caller-written perm must be a permutation of 0 .. n-1
+                       (entries out of range are skipped; a repeated entry makes two lanes race on one
+                       geodesic, with undefined results but no access outside the state).  Use it for
+                       geodesic sets in no particular order (particles); `order` keeps the 64 rays of a
+                       wave adjacent in memory, which suits images. */
 } kh_state;
 
 /* Integration rules.  Defaults (kh_default_params): DOPRI5, FP64,
@@ -187,6 +194,8 @@ void kh_default_params(kh_params *p);
  * r = 5, on a log scale; a tile takes the maximum over its rays and the tiles
  * are counting-sorted on that key (the order within a key is unspecified).  The
  * results of kh_integrate do not depend on the order, only its run time.
+ * st->perm, if set, gets the per-ray form of the same key (see
+ * kh_init_geodesics) and then takes precedence over the tile order.
  * Requires st->n == sum of width*height.  Writes s, spin, kind (KH_NULL),
  * h = 0, lam = 0, phi = atan2(y, x), status, n_acc = n_rej = 0, n_cross = 0,
  * cross = NaN and c0.  The camera table is copied to the context (one small
@@ -200,14 +209,26 @@ void kh_default_params(kh_params *p);
 kh_status kh_init_rays(kh_ctx *ctx, const kh_camera *cams, int32_t n_cams, kh_state *st, void *stream);
 
 /* Rays with individual parameters (device arrays [n]): physical spin, inclination,
- * alpha, beta; common image distance r_obs.  Same outputs as kh_init_rays. */
+ * alpha, beta; common image distance r_obs.  Same outputs as kh_init_rays;
+ * st->order gets the natural order and st->perm, if set, the ray-by-ray
+ * longest-first schedule of kh_init_geodesics. */
 kh_status kh_init_rays_list(kh_ctx *ctx, const double *spin, const double *incl, const double *alpha,
                             const double *beta, double r_obs, kh_state *st, void *stream);
 
 /* Geodesics from positions x3 [3][n] and spins [n] (device).  KH_TIMELIKE: v3
  * [3][n] is the coordinate velocity dx^i/dt and u^0 = 1/sqrt(-g_ab v^a v^b) with
  * v^0 = 1 (status KH_FAILED where that norm is not negative).  KH_NULL: v3 is
- * the spatial momentum and k^0 the future root of the null condition. */
+ * the spatial momentum and k^0 the future root of the null condition.
+ * st->order gets the natural order.  If st->perm is set, the call also writes
+ * a per-geodesic schedule, longest expected integration first, so that the
+ * launch does not end waiting for a few long geodesics started late: each
+ * geodesic gets a key (0 .. 255) and perm lists the geodesics by descending
+ * key (the order within a key is unspecified; kh_integrate's results do not
+ * depend on it).  Time-like key: the orbital time scale, the semi-major axis
+ * 1 / (2 (1 - E)) of a Newtonian orbit of the same binding energy (E = -u_t),
+ * on a log scale with 16 steps per octave, shorter first (steps to a fixed
+ * t_end scale as its power -3/2); unbound geodesics (E >= 1) get key 0.  Null
+ * key: the radial-potential priority of kh_init_rays, per ray. */
 kh_status kh_init_geodesics(kh_ctx *ctx, int32_t kind, const double *spin, const double *x3, const double *v3,
                             kh_state *st, void *stream);
 

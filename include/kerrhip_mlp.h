@@ -92,7 +92,8 @@ kh_status kh_mlp_train_step(kh_ctx *ctx, const kh_mlp *net, void *work, int32_t 
                             void *stream);
 
 /* Rays of the listed pixels of one camera: st->n = number of ids in pix
- * (device int32 [st->n]), same outputs as kh_init_rays. */
+ * (device int32 [st->n]), same outputs as kh_init_rays; st->order and
+ * st->perm, where set, get the natural order.  May be captured in a graph. */
 kh_status kh_init_rays_pixels(kh_ctx *ctx, const kh_camera *cam, const int32_t *pix, kh_state *st, void *stream);
 
 /* Write integrated rays into an image in the surrogate's format:

@@ -36,7 +36,7 @@ class kh_state(C.Structure):
                 ("h", C.c_void_p), ("lam", C.c_void_p), ("phi", C.c_void_p), ("status", C.c_void_p),
                 ("n_acc", C.c_void_p), ("n_rej", C.c_void_p), ("cross", C.c_void_p), ("n_cross", C.c_void_p),
                 ("k_cross", C.c_int32), ("c0", C.c_void_p), ("c1", C.c_void_p), ("order", C.c_void_p),
-                ("n_out", C.c_int32), ("t_out", C.c_void_p), ("s_out", C.c_void_p)]
+                ("n_out", C.c_int32), ("t_out", C.c_void_p), ("s_out", C.c_void_p), ("perm", C.c_void_p)]
 
 
 class kh_params(C.Structure):
@@ -395,12 +395,21 @@ _mlp_methods()
 
 
 class State:
-    """Structure-of-arrays geodesic state in device memory (torch tensors)."""
+    """Structure-of-arrays geodesic state in device memory (torch tensors).
 
-    def __init__(self, n: int, k_cross: int = 0, constants: bool = True, device="cuda", schedule: bool = True,
+    schedule: "tiles" (default; True is the same) allocates the 64-ray tile
+    order, which keeps a wave's rays adjacent (images); "geodesics" allocates
+    the per-geodesic schedule `perm` (sets in no particular order, such as
+    particles); None or False: natural order."""
+
+    def __init__(self, n: int, k_cross: int = 0, constants: bool = True, device="cuda", schedule="tiles",
                  t_out=None):
         if n < 1:
             raise ValueError("n must be >= 1")
+        if schedule is True:
+            schedule = "tiles"
+        if schedule not in ("tiles", "geodesics", None, False):
+            raise ValueError("schedule must be 'tiles', 'geodesics' or None")
         f64 = dict(dtype=torch.float64, device=device)
         i32 = dict(dtype=torch.int32, device=device)
         self.n = n
@@ -419,7 +428,9 @@ class State:
         self.c0 = torch.zeros((4, n), **f64) if constants else None
         self.c1 = torch.zeros((4, n), **f64) if constants else None
         # tile order for the integrator (written by the init calls); natural order until then
-        self.order = torch.arange((n + 63) // 64, **i32) if schedule else None
+        self.order = torch.arange((n + 63) // 64, **i32) if schedule == "tiles" else None
+        # per-geodesic schedule (replaces the tile order when present)
+        self.perm = torch.arange(n, **i32) if schedule == "geodesics" else None
         # dense output at ascending coordinate times: s_out [n][len(t_out)][8], NaN until reached
         if t_out is not None and len(t_out) > 0:
             self.t_out = torch.as_tensor(t_out, **f64).contiguous()
@@ -430,13 +441,13 @@ class State:
         p = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
         self.c = kh_state(n, p(self.s), p(self.spin), p(self.kind), p(self.h), p(self.lam), p(self.phi),
                           p(self.status), p(self.n_acc), p(self.n_rej), p(self.cross), p(self.n_cross), k_cross,
-                          p(self.c0), p(self.c1), p(self.order), n_out, p(self.t_out), p(self.s_out))
+                          p(self.c0), p(self.c1), p(self.order), n_out, p(self.t_out), p(self.s_out), p(self.perm))
 
     def numpy(self) -> dict:
         """Host copy of every array (for checks; synchronises)."""
         out = {}
         for name in ("s", "spin", "kind", "h", "lam", "phi", "status", "n_acc", "n_rej", "cross", "n_cross", "c0",
-                     "c1", "order", "s_out"):
+                     "c1", "order", "s_out", "perm"):
             t = getattr(self, name)
             out[name] = t.cpu().numpy() if t is not None else None
         return out

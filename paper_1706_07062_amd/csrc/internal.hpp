@@ -24,6 +24,9 @@ struct kh_ctx {
   hipEvent_t cam_evt = nullptr;
   uint8_t* d_keys = nullptr;  // per-tile scheduling keys of kh_init_rays
   int64_t keys_cap = 0;
+  uint8_t* d_gkeys = nullptr;  // per-geodesic scheduling keys (state.perm)
+  int64_t gkeys_cap = 0;
+  unsigned* d_perm_cnt = nullptr;  // 512 counters of the per-geodesic sort: counts, then next free position
   std::string err;
 };
 
@@ -46,6 +49,7 @@ struct KState {
   double* c0;
   double* c1;
   int32_t* order;  // tile permutation or nullptr
+  int32_t* perm;   // per-geodesic queue order or nullptr (replaces order)
   int32_t n_out;   // dense-output targets
   const double* t_out;
   double* s_out;
@@ -78,6 +82,7 @@ inline KState to_k(const kh_state* st) {
   k.c0 = st->c0;
   k.c1 = st->c1;
   k.order = st->order;
+  k.perm = st->perm;
   k.n_out = st->n_out;
   k.t_out = st->t_out;
   k.s_out = st->s_out;

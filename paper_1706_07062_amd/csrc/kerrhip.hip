@@ -30,7 +30,7 @@ using namespace khi;
 // The Python binding mirrors these layouts with ctypes.
 static_assert(sizeof(kh_camera) == 64, "kh_camera layout");
 static_assert(sizeof(kh_params) == 112, "kh_params layout");
-static_assert(sizeof(kh_state) == 152, "kh_state layout");
+static_assert(sizeof(kh_state) == 160, "kh_state layout");
 
 namespace {
 
@@ -141,11 +141,16 @@ __device__ inline int64_t wave_grab(unsigned long long idle, unsigned long long*
   return -1;
 }
 
-// Queue position -> ray id: through the tile order when there is one.  Every
-// index is checked, so a malformed order can skip rays but never read or write
-// outside the state.
+// Queue position -> ray id: through the per-geodesic schedule or the tile
+// order when there is one.  Every index is checked, so a malformed order can
+// skip rays but never read or write outside the state.
 __device__ inline int64_t queue_id(int64_t pos, const KState& S, int64_t n_tiles) {
-  if (pos < 0 || !S.order) return pos;
+  if (pos < 0) return pos;
+  if (S.perm) {
+    const int64_t id = pos < S.n ? (int64_t)S.perm[pos] : -1;
+    return (id >= 0 && id < S.n) ? id : -1;
+  }
+  if (!S.order) return pos;
   const int64_t t = pos >> 6;
   if (t >= n_tiles) return -1;
   const int64_t tile = S.order[t];
@@ -232,7 +237,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
   const int home = blockIdx.x % parts;
   // with a tile order the queue runs over whole tiles (ids past n are skipped)
   const int64_t n_tiles = (n + 63) >> 6;
-  const int64_t nq = S.order ? n_tiles * 64 : n;
+  const int64_t nq = (S.order && !S.perm) ? n_tiles * 64 : n;
   int cursor = 0;  // partitions this wave has seen drained (wave-uniform)
   bool fresh = false;
 
@@ -694,9 +699,26 @@ __device__ inline int ray_priority(double a, const double y[8]) {
   return key < 0 ? 0 : (key > 255 ? 255 : key);
 }
 
+// Scheduling priority of a time-like geodesic (0 .. 255, larger = more steps to
+// a common t_end expected): the steps scale with t_end over the orbital period,
+// i.e. as A^{-3/2} with A = 1 / (2 (1 - E)) the semi-major axis of a Newtonian
+// orbit of the same binding energy.  16 keys per octave of A; unbound or
+// undefined energies get 0.
+__device__ inline int timelike_priority(double a, const double y[8]) {
+  double cst[4];
+  constants(a, y, y + 4, cst);
+  const double E = cst[0];
+  if (!(E > 0.0 && E < 1.0)) return 0;
+  const double A = 0.5 / (1.0 - E);
+  const double k = 255.0 - 16.0 * log2(A > 1.0 ? A : 1.0);
+  return k < 0.0 ? 0 : (int)k;
+}
+
 // keys (optional): per-tile scheduling key, the maximum of ray_priority over
 // the tile's 64 rays (one wave = one tile: blocks are multiples of 64 threads).
-__global__ void k_init_rays(const kh_camera* cams, const int64_t* offs, int n_cams, KState S, uint8_t* keys) {
+// gkeys (optional): the per-ray key itself.
+__global__ void k_init_rays(const kh_camera* cams, const int64_t* offs, int n_cams, KState S, uint8_t* keys,
+                            uint8_t* gkeys) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int key = 0;
   if (i < S.n) {
@@ -717,7 +739,8 @@ __global__ void k_init_rays(const kh_camera* cams, const int64_t* offs, int n_ca
     bool ok;
     camera_ray(cam.a, cam.r_obs, cam.incl, al, be, y, &ok);
     finish_init(S, i, y, cam.a, KH_NULL, ok);
-    if (keys && ok) key = ray_priority(-cam.a, y);
+    if ((keys || gkeys) && ok) key = ray_priority(-cam.a, y);
+    if (gkeys) gkeys[i] = (uint8_t)key;
   }
   if (keys) {
 #pragma unroll
@@ -757,6 +780,71 @@ __global__ void k_order_identity(int32_t* order, int64_t n_tiles) {
   if (t < n_tiles) order[t] = (int32_t)t;
 }
 
+// Per-geodesic counting sort of 8-bit keys, largest first, into perm [n]:
+// clear the 256 counts, count (one LDS histogram per block of kPermSpan keys),
+// scan in one block, then each block reserves its run of every key with one
+// global atomic and places its geodesics by LDS atomics (the order within a
+// key is unspecified).  cnt [0, 256) holds the counts, cnt [256, 512) the next
+// free position of each key.
+constexpr int kPermThreads = 256;
+constexpr int kPermSpan = 8192;
+
+__global__ void __launch_bounds__(kPermThreads) k_perm_clear(unsigned* cnt) {
+  cnt[threadIdx.x] = 0u;
+}
+
+__global__ void __launch_bounds__(kPermThreads) k_perm_count(const uint8_t* keys, int64_t n, unsigned* cnt) {
+  __shared__ unsigned hist[256];
+  hist[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * kPermSpan;
+  const int64_t hi = lo + kPermSpan < n ? lo + kPermSpan : n;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kPermThreads) atomicAdd(&hist[keys[i]], 1u);
+  __syncthreads();
+  if (hist[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], hist[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(kPermThreads) k_perm_scan(unsigned* cnt) {
+  __shared__ unsigned v[256];
+  const int t = threadIdx.x;  // position t of the descending key order holds key 255 - t
+  const unsigned mine = cnt[255 - t];
+  v[t] = mine;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const unsigned add = t >= o ? v[t - o] : 0u;
+    __syncthreads();
+    v[t] += add;
+    __syncthreads();
+  }
+  cnt[256 + 255 - t] = v[t] - mine;
+}
+
+__global__ void __launch_bounds__(kPermThreads) k_perm_scatter(const uint8_t* keys, int64_t n, unsigned* cnt,
+                                                             int32_t* perm) {
+  __shared__ unsigned hist[256];
+  __shared__ unsigned base[256];
+  hist[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * kPermSpan;
+  const int64_t hi = lo + kPermSpan < n ? lo + kPermSpan : n;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kPermThreads) atomicAdd(&hist[keys[i]], 1u);
+  __syncthreads();
+  const unsigned c = hist[threadIdx.x];
+  base[threadIdx.x] = c ? atomicAdd(&cnt[256 + threadIdx.x], c) : 0u;
+  hist[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kPermThreads) {
+    const int k = keys[i];
+    const unsigned pos = base[k] + atomicAdd(&hist[k], 1u);
+    perm[pos] = (int32_t)i;
+  }
+}
+
+__global__ void k_perm_identity(int32_t* perm, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) perm[i] = (int32_t)i;
+}
+
 __global__ void k_init_rays_pixels(kh_camera cam, const int32_t* pix, KState S) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.n) return;
@@ -771,16 +859,18 @@ __global__ void k_init_rays_pixels(kh_camera cam, const int32_t* pix, KState S) 
 }
 
 __global__ void k_init_rays_list(const double* spin, const double* incl, const double* alpha, const double* beta,
-                                 double r_obs, KState S) {
+                                 double r_obs, KState S, uint8_t* gkeys) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.n) return;
   double y[8];
   bool ok;
   camera_ray(spin[i], r_obs, incl[i], alpha[i], beta[i], y, &ok);
   finish_init(S, i, y, spin[i], KH_NULL, ok);
+  if (gkeys) gkeys[i] = (uint8_t)(ok ? ray_priority(-spin[i], y) : 0);
 }
 
-__global__ void k_init_geodesics(int kind, const double* spin, const double* x3, const double* v3, KState S) {
+__global__ void k_init_geodesics(int kind, const double* spin, const double* x3, const double* v3, KState S,
+                                 uint8_t* gkeys) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = S.n;
   if (i >= n) return;
@@ -797,7 +887,9 @@ __global__ void k_init_geodesics(int kind, const double* spin, const double* x3,
   } else {
     y[4] = null_k0(-a, y, y + 4, &ok);
   }
-  finish_init(S, i, y, a, kind, ok && (y[4] == y[4]));
+  ok = ok && (y[4] == y[4]);
+  finish_init(S, i, y, a, kind, ok);
+  if (gkeys) gkeys[i] = (uint8_t)(!ok ? 0 : (kind == KH_TIMELIKE ? timelike_priority(a, y) : ray_priority(-a, y)));
 }
 
 // ---------------------------------------------------------------------------
@@ -963,6 +1055,8 @@ kh_status check_state(kh_ctx* ctx, const kh_state* st, bool need_cross) {
     return fail(ctx, KH_EINVAL, "state.n_cross must be NULL or 4-byte aligned device memory");
   if (st->order && (!aligned(st->order, 4) || !device_ok(st->order)))
     return fail(ctx, KH_EINVAL, "state.order must be NULL or 4-byte aligned device memory");
+  if (st->perm && (!aligned(st->perm, 4) || !device_ok(st->perm)))
+    return fail(ctx, KH_EINVAL, "state.perm must be NULL or 4-byte aligned device memory");
   if (st->n_out < 0) return fail(ctx, KH_EINVAL, "state.n_out must be >= 0");
   if (st->n_out > 0 && (!st->t_out || !st->s_out || !aligned(st->t_out, 8) || !aligned(st->s_out, 8) ||
                         !device_ok(st->t_out) || !device_ok(st->s_out)))
@@ -1064,6 +1158,7 @@ kh_status kh_create(kh_ctx** out, int device) {
       hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
       hipMalloc(&c->d_queue, kQueueSlots * sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&c->d_stats, 8 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&c->d_perm_cnt, 512 * sizeof(unsigned)) != hipSuccess ||
       hipEventCreateWithFlags(&c->cam_evt, hipEventDisableTiming) != hipSuccess) {
     kh_destroy(c);
     return KH_ENOMEM;
@@ -1084,6 +1179,8 @@ kh_status kh_destroy(kh_ctx* c) {
   if (c->h_offs) (void)hipHostFree(c->h_offs);
   if (c->cam_evt) (void)hipEventDestroy(c->cam_evt);
   if (c->d_keys) (void)hipFree(c->d_keys);
+  if (c->d_gkeys) (void)hipFree(c->d_gkeys);
+  if (c->d_perm_cnt) (void)hipFree(c->d_perm_cnt);
   delete c;
   return KH_OK;
 }
@@ -1091,11 +1188,45 @@ kh_status kh_destroy(kh_ctx* c) {
 const char* kh_last_error(const kh_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
 
 namespace {
+// Per-geodesic key buffer of at least st->n bytes (NULL without st->perm).  It
+// grows only outside graph capture.
+kh_status geodesic_keys(kh_ctx* ctx, const kh_state* st, uint8_t** out) {
+  *out = nullptr;
+  if (!st->perm) return KH_OK;
+  if (st->n > ctx->gkeys_cap) {
+    if (g_skip_ptr_query)
+      return fail(ctx, KH_EINVAL, "the geodesic-key buffer must grow: call the init once outside graph capture");
+    if (ctx->d_gkeys) KH_HIP(ctx, hipFree(ctx->d_gkeys));
+    ctx->d_gkeys = nullptr;
+    ctx->gkeys_cap = 0;
+    if (hipMalloc(&ctx->d_gkeys, (size_t)st->n) != hipSuccess) return fail(ctx, KH_ENOMEM, "geodesic-key buffer");
+    ctx->gkeys_cap = st->n;
+  }
+  *out = ctx->d_gkeys;
+  return KH_OK;
+}
+
+// Counting sort of the per-geodesic keys into st->perm (four launches).
+kh_status sort_perm(kh_ctx* ctx, const kh_state* st, const uint8_t* gkeys, hipStream_t strm) {
+  const unsigned blocks = (unsigned)((st->n + kPermSpan - 1) / kPermSpan);
+  hipLaunchKernelGGL(k_perm_clear, dim3(1), dim3(kPermThreads), 0, strm, ctx->d_perm_cnt);
+  hipLaunchKernelGGL(k_perm_count, dim3(blocks), dim3(kPermThreads), 0, strm, gkeys, st->n, ctx->d_perm_cnt);
+  hipLaunchKernelGGL(k_perm_scan, dim3(1), dim3(kPermThreads), 0, strm, ctx->d_perm_cnt);
+  hipLaunchKernelGGL(k_perm_scatter, dim3(blocks), dim3(kPermThreads), 0, strm, gkeys, st->n, ctx->d_perm_cnt,
+                     st->perm);
+  KH_HIP(ctx, hipGetLastError());
+  return KH_OK;
+}
+
 // The init kernel over the uploaded camera table, then (with st->order) the
-// tile sort.  The key buffer grows only outside graph capture.
+// tile sort and (with st->perm) the per-ray sort.  The key buffers grow only
+// outside graph capture.
 kh_status launch_init_rays(kh_ctx* ctx, kh_state* st, int n_cams, hipStream_t strm) {
   const int64_t n_tiles = (st->n + 63) / 64;
   uint8_t* keys = nullptr;
+  uint8_t* gkeys = nullptr;
+  kh_status s = geodesic_keys(ctx, st, &gkeys);
+  if (s != KH_OK) return s;
   if (st->order) {
     if (n_tiles > ctx->keys_cap) {
       if (g_skip_ptr_query)
@@ -1112,20 +1243,28 @@ kh_status launch_init_rays(kh_ctx* ctx, kh_state* st, int n_cams, hipStream_t st
   const int block = 256;
   const int64_t grid = (st->n + block - 1) / block;
   hipLaunchKernelGGL(k_init_rays, dim3((unsigned)grid), dim3(block), 0, strm, ctx->d_cams, ctx->d_offs, n_cams, ks,
-                     keys);
+                     keys, gkeys);
   KH_HIP(ctx, hipGetLastError());
   if (st->order) {
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kSortThreads), 0, strm, (const uint8_t*)keys, n_tiles, st->order);
     KH_HIP(ctx, hipGetLastError());
   }
-  return KH_OK;
+  return gkeys ? sort_perm(ctx, st, gkeys, strm) : KH_OK;
 }
 
-kh_status natural_order(kh_ctx* ctx, const kh_state* st, hipStream_t strm) {
-  if (!st->order) return KH_OK;
-  const int64_t n_tiles = (st->n + 63) / 64;
-  hipLaunchKernelGGL(k_order_identity, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, strm, st->order, n_tiles);
-  KH_HIP(ctx, hipGetLastError());
+// Natural tile order, and the natural per-geodesic order unless `sorted`
+// (the caller then sorts st->perm itself).
+kh_status natural_order(kh_ctx* ctx, const kh_state* st, hipStream_t strm, bool sorted = false) {
+  if (st->order) {
+    const int64_t n_tiles = (st->n + 63) / 64;
+    hipLaunchKernelGGL(k_order_identity, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, strm, st->order,
+                       n_tiles);
+    KH_HIP(ctx, hipGetLastError());
+  }
+  if (st->perm && !sorted) {
+    hipLaunchKernelGGL(k_perm_identity, dim3((unsigned)((st->n + 255) / 256)), dim3(256), 0, strm, st->perm, st->n);
+    KH_HIP(ctx, hipGetLastError());
+  }
   return KH_OK;
 }
 }  // namespace
@@ -1207,13 +1346,16 @@ kh_status kh_init_rays_list(kh_ctx* ctx, const double* spin, const double* incl,
       return fail(ctx, KH_EINVAL, "spin, incl, alpha, beta must be 8-byte aligned device arrays of length n");
   if (!(r_obs > 0.0)) return fail(ctx, KH_EINVAL, "r_obs must be > 0");
   if ((s = set_device(ctx)) != KH_OK) return s;
+  uint8_t* gkeys = nullptr;
+  if ((s = geodesic_keys(ctx, st, &gkeys)) != KH_OK) return s;
   const KState ks = to_k(st);
   const int block = 256;
   const int64_t grid = (st->n + block - 1) / block;
   hipLaunchKernelGGL(k_init_rays_list, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)stream, spin, incl, alpha,
-                     beta, r_obs, ks);
+                     beta, r_obs, ks, gkeys);
   KH_HIP(ctx, hipGetLastError());
-  return natural_order(ctx, st, (hipStream_t)stream);
+  if ((s = natural_order(ctx, st, (hipStream_t)stream, gkeys != nullptr)) != KH_OK) return s;
+  return gkeys ? sort_perm(ctx, st, gkeys, (hipStream_t)stream) : KH_OK;
 }
 
 kh_status kh_init_rays_pixels(kh_ctx* ctx, const kh_camera* cam, const int32_t* pix, kh_state* st, void* stream) {
@@ -1245,13 +1387,16 @@ kh_status kh_init_geodesics(kh_ctx* ctx, int32_t kind, const double* spin, const
     if (!p || !aligned(p, 8) || !is_device_ptr(p))
       return fail(ctx, KH_EINVAL, "spin [n], x3 [3][n], v3 [3][n] must be 8-byte aligned device arrays");
   if ((s = set_device(ctx)) != KH_OK) return s;
+  uint8_t* gkeys = nullptr;
+  if ((s = geodesic_keys(ctx, st, &gkeys)) != KH_OK) return s;
   const KState ks = to_k(st);
   const int block = 256;
   const int64_t grid = (st->n + block - 1) / block;
   hipLaunchKernelGGL(k_init_geodesics, dim3((unsigned)grid), dim3(block), 0, (hipStream_t)stream, (int)kind, spin,
-                     x3, v3, ks);
+                     x3, v3, ks, gkeys);
   KH_HIP(ctx, hipGetLastError());
-  return natural_order(ctx, st, (hipStream_t)stream);
+  if ((s = natural_order(ctx, st, (hipStream_t)stream, gkeys != nullptr)) != KH_OK) return s;
+  return gkeys ? sort_perm(ctx, st, gkeys, (hipStream_t)stream) : KH_OK;
 }
 
 kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stream) {

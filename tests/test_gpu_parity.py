@@ -384,6 +384,116 @@ def test_out_of_range_tile_order_is_skipped(ctx):
     assert np.all(g["status"][64:192] != K.ACTIVE)
 
 
+def _is_permutation(perm, n):
+    return perm.shape == (n,) and np.array_equal(np.sort(perm), np.arange(n))
+
+
+def test_geodesic_schedule_orders_particles_longest_first(ctx):
+    """kh_init_geodesics with a per-geodesic schedule: perm is a permutation of
+    the geodesics (several sort blocks of 8192 and a ragged tail), its keys
+    descend (the key is recomputed here from the energy E in c0:
+    255 - 16 log2(1 / (2 (1 - E))), truncated), the geodesics it puts first
+    take more steps, and the results are bitwise those of the natural order."""
+    say("geodesic schedule, particles")
+    n = 3 * 8192 + 77
+    pw = W.particles(n=n)
+    t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()  # noqa: E731
+    p = K.kh_default_params(t_end=1e4, r_escape=1e4)
+    runs = {}
+    for sched in ("geodesics", None):
+        st = K.State(n, schedule=sched)
+        ctx.kh_init_geodesics(K.TIMELIKE, t(pw["a"]), t(pw["x3"]), t(pw["v3"]), st)
+        if sched:
+            perm0 = st.perm.cpu().numpy()
+        ctx.kh_integrate(p, st)
+        torch.cuda.synchronize()
+        runs[sched] = st.numpy()
+    a, b = runs["geodesics"], runs[None]
+    for name in ("s", "status", "n_acc", "n_rej", "lam", "h", "c1"):
+        assert np.array_equal(a[name], b[name], equal_nan=True), name
+    assert _is_permutation(perm0, n)
+    E = a["c0"][0]
+    bound = (E > 0) & (E < 1)
+    kf = np.where(bound, 255.0 - 16.0 * np.log2(np.maximum(0.5 / np.where(bound, 1.0 - E, 1.0), 1.0)), 0.0)
+    kf = np.clip(kf, 0.0, 255.0)
+    kh = np.floor(kf)[perm0]
+    near_int = np.abs(kf - np.round(kf))[perm0] < 1e-9
+    drops = np.diff(kh)
+    assert np.all((drops <= 0) | near_int[1:] | near_int[:-1])
+    cost = (a["n_acc"] + a["n_rej"]).astype(np.float64)[perm0]
+    head, tail = cost[: n // 10].mean(), cost[-n // 10:].mean()
+    say(f"  mean steps: first tenth of the schedule {head:.0f}, last tenth {tail:.0f}, max {cost.max():.0f}")
+    assert head > 4 * tail
+    assert cost.argmax() < n // 10
+
+
+def test_geodesic_schedule_for_rays_and_images(ctx):
+    """The per-ray schedule from kh_init_rays_list and kh_init_rays is a
+    permutation, puts the costliest rays first, and leaves the results
+    bitwise unchanged (against the tile order of the same image)."""
+    say("geodesic schedule, rays")
+    cams = [W.Camera(0.99, 1000.0, 60.0, -12.0, 12.0, -12.0, 12.0, 97, 83),
+            W.Camera(0.5, 1000.0, 30.0, -9.0, 11.0, -10.0, 10.0, 61, 45)]
+    n = sum(c.n for c in cams)
+    p = K.kh_default_params(k_cross=4)
+    tiles = gpu_image(ctx, cams, p, k_cross=4).numpy()
+    st = K.State(n, k_cross=4, schedule="geodesics")
+    ctx.kh_init_rays([kcam(c) for c in cams], st)
+    perm = st.perm.cpu().numpy()
+    ctx.kh_integrate(p, st)
+    torch.cuda.synchronize()
+    g = st.numpy()
+    assert _is_permutation(perm, n)
+    for name in ("s", "status", "n_acc", "n_rej", "cross", "n_cross", "phi", "lam", "h"):
+        assert np.array_equal(g[name], tiles[name], equal_nan=True), name
+    cost = (g["n_acc"] + g["n_rej"]).astype(np.float64)
+    head = cost[perm[: n // 10]]
+    say(f"  mean steps: first tenth of the schedule {head.mean():.0f}, all rays {cost.mean():.0f}")
+    assert head.mean() > cost.mean()
+    assert cost.max() in head
+    # the list form (one spin and inclination per ray): scheduled and natural
+    # order give the same bits
+    c = cams[0]
+    f64 = dict(dtype=torch.float64, device="cuda")
+    col = np.arange(c.n) % c.width
+    row = np.arange(c.n) // c.width
+    args = (torch.full((c.n,), c.a, **f64), torch.full((c.n,), c.incl, **f64),
+            torch.from_numpy(c.alpha_min + (col + 0.5) * (c.alpha_max - c.alpha_min) / c.width).cuda(),
+            torch.from_numpy(c.beta_min + (row + 0.5) * (c.beta_max - c.beta_min) / c.height).cuda(), c.r_obs)
+    out = {}
+    for sched in ("geodesics", None):
+        sl = K.State(c.n, k_cross=4, schedule=sched)
+        ctx.kh_init_rays_list(*args, sl)
+        if sched:
+            assert _is_permutation(sl.perm.cpu().numpy(), c.n)
+        ctx.kh_integrate(p, sl)
+        torch.cuda.synchronize()
+        out[sched] = sl.numpy()
+    for name in ("s", "status", "n_acc", "cross"):
+        assert np.array_equal(out["geodesics"][name], out[None][name], equal_nan=True), name
+
+
+def test_out_of_range_geodesic_schedule_is_skipped(ctx):
+    """A caller-written perm with entries out of range: those positions are
+    skipped (no access outside the state) and the geodesics they would have
+    named stay active; the tile order is ignored while perm is set."""
+    say("bad geodesic schedule")
+    cam = W.kerr_image(60.0, side=16)
+    st = K.State(cam.n, schedule="geodesics")
+    ctx.kh_init_rays([kcam(cam)], st)
+    bad = torch.arange(cam.n, dtype=torch.int32, device="cuda")
+    bad[10] = cam.n
+    bad[20] = -1
+    bad[30] = 1 << 30
+    st.perm.copy_(bad)
+    ctx.kh_integrate(K.kh_default_params(), st)
+    torch.cuda.synchronize()
+    status = st.status.cpu().numpy()
+    skipped = np.array([10, 20, 30])
+    assert np.all(status[skipped] == K.ACTIVE)
+    assert np.all(np.delete(status, skipped) != K.ACTIVE)
+
+
 def test_coordinate_time_image_parity(ctx):
     """Null rays of a ragged a = 0.99 image integrated in coordinate time
     (KH_DOPRI5_T, rtol 1e-8, four crossing slots) against the oracle's

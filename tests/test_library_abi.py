@@ -53,7 +53,7 @@ def test_default_params_and_struct_layout():
     # struct sizes agree with the C layout (8-byte aligned doubles)
     assert C.sizeof(K.kh_camera) == 64
     assert C.sizeof(K.kh_params) == 112
-    assert C.sizeof(K.kh_state) == 8 * 19
+    assert C.sizeof(K.kh_state) == 8 * 20
     assert C.sizeof(K.kh_flop_counts) == 8 * 9
     assert C.sizeof(K.kh_fixed_params) == 16 + 8 * 4
 
