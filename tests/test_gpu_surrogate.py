@@ -129,6 +129,58 @@ def test_image_kernel_decodes_forward_and_lists_fallback(ctx):
     assert np.abs(raw - ref).max() / np.abs(ref).max() < 2e-2
 
 
+def test_image_kernel_full_size_sampled(ctx):
+    """The image kernel at the inference size the benchmark renders (the
+    4096x4096 camera at a = 0.9, 45 deg): 4,096 pixels spread over the image
+    match the FP64 reference network with BF16 storage, decoded; and the
+    fallback list holds exactly the pixels whose capture probability lies in
+    (tau, 1 - tau), each once."""
+    say("mlp image kernel, 4096^2")
+    p = S.init_params(14)
+    p[M.NPARAMS - 4:] = [0.1, 0.2, -0.1, 0.4]
+    net = K.Mlp(p, train=False)
+    ctx.kh_mlp_sync(net)
+    cam = W.surrogate_eval_camera()
+    n = cam.n
+    tau = 0.05
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    ids = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.kh_mlp_image(net, S.camera_struct(cam), tau, out, ids, cnt)
+    torch.cuda.synchronize()
+    img = out.cpu().numpy().astype(np.float64)
+    assert np.isfinite(img).all()
+    pix = W.strided_pixels(n, 4096, offset=17)
+    col, row = pix % cam.width, pix // cam.width
+    al = cam.alpha_min + (col + 0.5) * (cam.alpha_max - cam.alpha_min) / cam.width
+    be = cam.beta_min + (row + 0.5) * (cam.beta_max - cam.beta_min) / cam.height
+    x = np.stack([al, be, np.full(len(pix), cam.a), np.full(len(pix), cam.incl)], axis=1).astype(np.float32)
+    ref, _ = M.forward(p.astype(np.float64), x.astype(np.float64), bf16_storage=True)
+    # compare in the raw (pre-decode) outputs: invert the decode of the kernel
+    got = img[pix]
+    raw = np.stack([(np.log(got[:, 0]) - 2) / 2, got[:, 1] / np.pi, (got[:, 2] - 0.8) / 0.3,
+                    np.log(got[:, 3] / (1 - got[:, 3]))], axis=1)
+    err = np.abs(raw - ref).max() / np.abs(ref).max()
+    say(f"  sampled raw-output error / max |y| = {err:.2e}")
+    assert err < 2e-2
+    pc = img[:, 3]
+    # a second threshold that lists about half of the image
+    tau2 = float(np.quantile(np.minimum(pc, 1 - pc), 0.5))
+    for t_, first in ((tau, True), (tau2, False)):
+        if not first:
+            ids.fill_(-1)
+            cnt.zero_()
+            ctx.kh_mlp_image(net, S.camera_struct(cam), t_, out, ids, cnt)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), img.astype(np.float32))
+        k = int(cnt.item())
+        listed = ids.cpu().numpy()[:k]
+        want = np.nonzero((pc > t_) & (pc < 1 - t_))[0]
+        say(f"  tau {t_:.4f}: {k} fallback pixels of {n}")
+        assert len(np.unique(listed)) == k
+        assert np.array_equal(np.sort(listed), want)
+
+
 def test_forward_single_ray_and_one_past_a_block(ctx):
     p = S.init_params(13)
     net = K.Mlp(p, train=False)
