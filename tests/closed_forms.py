@@ -148,3 +148,76 @@ def bl_metric(r, th, a):
     g[2, 2] = rho2
     g[3, 3] = (r * r + a * a + 2 * r * a * a * s2 / rho2) * s2
     return g
+
+
+def schwarzschild_crossings(x0, v0, k_max, r_capture, r_escape):
+    """Equatorial crossings of a Schwarzschild (a = 0) photon from the orbit
+    equation, independently of any integrator.
+
+    x0, v0: initial Cartesian position and spatial velocity dx^i/dlambda (the
+    spatial coordinates of the Kerr-Schild chart are those of Schwarzschild
+    at a = 0, so the path is the textbook one).  The photon moves in the plane
+    of x0 and v0; with u = 1/r and the in-plane angle psi from x0,
+    (du/dpsi)^2 = P(u) = 1/b^2 - u^2 + 2 u^3, where b^2 = L^2 / (rdot^2 +
+    L^2 u^2 (1 - 2u)) (null condition), L = |x0 x v0|.  Crossings of z = 0 are
+    at psi_j = psi_1 + (j - 1) pi.  The angle integrals are taken with the
+    cubic's roots factored out (smooth integrands through the turning point).
+    Returns [(r_j, azimuth_j)] for the crossings reached before the photon
+    falls below r_capture or leaves past r_escape.
+    """
+    from scipy.optimize import brentq
+
+    x0, v0 = np.asarray(x0, float), np.asarray(v0, float)
+    r0 = np.linalg.norm(x0)
+    xh = x0 / r0
+    rdot = v0 @ xh
+    assert rdot < 0.0, "the photon must start inward"
+    w = v0 - rdot * xh
+    Lw = np.linalg.norm(w)
+    if Lw < 1e-12 * np.linalg.norm(v0):
+        return []  # radial: the photon keeps the sign of z until r = 0
+    wh = w / Lw
+    L = r0 * Lw
+    u0 = 1.0 / r0
+    b2 = L * L / (rdot * rdot + L * L * u0 * u0 * (1.0 - 2.0 * u0))
+    c = 1.0 / b2
+    th = np.arctan2(-xh[2], wh[2])
+    psi1 = th % np.pi
+    if psi1 == 0.0:
+        psi1 = np.pi
+    roots = np.sort(np.roots([2.0, -1.0, 0.0, c]).real[np.abs(np.roots([2.0, -1.0, 0.0, c]).imag) < 1e-12])
+    u_cap, u_esc = 1.0 / r_capture, 1.0 / r_escape
+    out = []
+
+    def point(psi, u):
+        p = np.cos(psi) * xh + np.sin(psi) * wh
+        return (1.0 / u, float(np.arctan2(p[1], p[0])))
+
+    if c < 1.0 / 27.0 and len(roots) == 3 and roots[1] > u0:
+        rn, ut, r3 = roots  # P(u) = 2 (u - rn)(u - ut)(u - r3), u0 < ut < r3
+        g = lambda s: 2.0 / np.sqrt(2.0 * (ut - s * s - rn) * (r3 - ut + s * s))  # noqa: E731
+        G = lambda s: integrate.quad(g, 0.0, s, epsabs=1e-14, epsrel=1e-13, limit=200)[0]  # noqa: E731
+        s0 = np.sqrt(ut - u0)
+        G0 = G(s0)
+        s_esc = np.sqrt(ut - u_esc)
+        G_esc = G(s_esc)
+        for j in range(k_max):
+            psi = psi1 + j * np.pi
+            if psi <= G0:  # inward branch: psi = G0 - G(s)
+                s = brentq(lambda s: G0 - G(s) - psi, 0.0, s0, xtol=1e-15)
+            elif psi - G0 < G_esc:  # outward branch: psi = G0 + G(s)
+                s = brentq(lambda s: G0 + G(s) - psi, 0.0, s_esc, xtol=1e-15)
+            else:
+                break
+            out.append(point(psi, ut - s * s))
+    else:  # no turning point: the photon falls in
+        f = lambda u: 1.0 / np.sqrt(c - u * u + 2.0 * u ** 3)  # noqa: E731
+        F = lambda u: integrate.quad(f, u0, u, epsabs=1e-14, epsrel=1e-13, limit=200)[0]  # noqa: E731
+        F_cap = F(u_cap)
+        for j in range(k_max):
+            psi = psi1 + j * np.pi
+            if psi >= F_cap:
+                break
+            u = brentq(lambda u: F(u) - psi, u0, u_cap, xtol=1e-16)
+            out.append(point(psi, u))
+    return out

@@ -448,6 +448,45 @@ def test_image_constants_conserved_and_mirror_symmetry():
     np.testing.assert_allclose(o1["cross"][..., 1], -o2["cross"][..., 1], rtol=1e-9, atol=1e-12)
 
 
+def test_schwarzschild_crossings_match_orbit_equation():
+    """a = 0: every equatorial-crossing record (count, radius, azimuth) of the
+    oracle equals the crossings of the textbook photon orbit, found by
+    quadrature of (du/dpsi)^2 = 1/b^2 - u^2 + 2u^3 in the plane of the initial
+    position and velocity (tests/closed_forms.py).  Rays of a 41x41 image
+    over [-8, 8]^2 at 60 deg (direct, captured and once-wound rays) and a
+    beta = 0 cut through the photon ring, b in [5.0, 5.6] and a finer one
+    in [5.18, 5.26] (up to four crossings); rays within 2e-3 of b = sqrt(27)
+    are left out (there the crossing radius changes by more than the
+    tolerance per 1e-10 of b).  DOPRI5 rtol 1e-12 with the
+    step cap at 0.01 r keeps the Hermite localisation error below the
+    tolerances."""
+    rays = [O.camera_rays(0.0, 1000.0, np.radians(60), -8, 8, -8, 8, 41, 41, pix=np.arange(0, 41 * 41, 13)),
+            O.camera_rays(0.0, 1000.0, np.radians(60), 5.0, 5.6, -0.5, 0.5, 61, 1),
+            O.camera_rays(0.0, 1000.0, np.radians(60), 5.18, 5.26, -0.5, 0.5, 41, 1)]
+    p = O.Params(method=O.DOPRI5, k_cross=4, rtol=1e-12, atol=1e-12, hmax_coeff=0.01)
+    n_checked = n_multi = 0
+    for init in rays:
+        out = O.integrate(init, p)
+        s = init["s"]
+        for i in range(s.shape[1]):
+            x, v = s[1:4, i], s[5:8, i]
+            L = np.linalg.norm(np.cross(x, v))
+            rdot = x @ v / np.linalg.norm(x)
+            u0 = 1 / np.linalg.norm(x)
+            b = L / np.sqrt(rdot ** 2 + L * L * u0 * u0 * (1 - 2 * u0))
+            if abs(b - np.sqrt(27.0)) < 2e-3:
+                continue
+            want = cf.schwarzschild_crossings(x, v, 4, 2.02, 1000.0)
+            assert min(out["n_cross"][i], 4) == len(want), (i, b)
+            for j, (r, ph) in enumerate(want):
+                got = out["cross"][i, j]
+                assert abs(got[0] - r) <= 1e-8 * r, (i, j, got[0], r)
+                assert abs((got[1] - ph + np.pi) % (2 * np.pi) - np.pi) < 1e-9, (i, j)
+            n_checked += 1
+            n_multi += len(want) >= 3
+    assert n_checked > 150 and n_multi >= 5
+
+
 def test_redshift_formula_matches_normalised_four_velocity():
     """The Keplerian u^t in the redshift equals the normalisation of
     u = u^t (1, Omega zhat x x) in the Cartesian metric (prograde, spin +a)."""
