@@ -139,7 +139,7 @@ typedef struct {
   int64_t max_steps; /* accepted steps per call before KH_MAX_STEPS (> 0) */
   int32_t block_size;   /* threads per block: 64, 128, 192 or 256; 0 = 256 */
   int32_t grid_blocks;  /* persistent grid size; 0 = fill the device from the occupancy query */
-  int32_t refill_min;   /* a wave refills once at least this many lanes are idle (1..64); 0 = 16 */
+  int32_t refill_min;   /* a wave refills once at least this many lanes are idle (1..64); 0 = 12 */
   int32_t waves_per_eu; /* register budget of the kernel variant (minimum waves per SIMD): 1 = two or more
                            waves; DOPRI5 with the factored form also has 3 and 4 (FP64 / mixed) and 4 and 5
                            (FP32); 0 = default (3 for mixed-precision DOPRI5, else 1) */

@@ -33,7 +33,7 @@ WAVE_VARIANTS = {P64: (1, 3, 4), P32: (1, 4, 5), PMIXED: (1, 3, 4)}
 def candidates(params: kh_params):
     waves = WAVE_VARIANTS.get(params.precision, (1,)) if (params.method == DOPRI5 and
                                                           params.rhs_form == RHS_FACTORED) else (1,)
-    for block, wpe, refill in itertools.product((64, 128, 256), waves, (4, 8, 16)):
+    for block, wpe, refill in itertools.product((64, 128, 256), waves, (4, 8, 12, 16)):
         yield dict(block_size=block, waves_per_eu=wpe, refill_min=refill)
 
 

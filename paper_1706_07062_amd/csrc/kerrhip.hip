@@ -1421,7 +1421,7 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
     return fail(ctx, KH_EUNSUPPORTED, "the paper-form right-hand side is built for P64 and P32 only");
   const int block = p->block_size ? p->block_size : 256;
   if (block < 64 || block > 256 || block % 64) return fail(ctx, KH_EINVAL, "block_size must be 64, 128, 192 or 256");
-  const int refill = p->refill_min ? p->refill_min : 16;
+  const int refill = p->refill_min ? p->refill_min : 12;
   if (refill < 1 || refill > 64) return fail(ctx, KH_EINVAL, "refill_min must be in [1, 64]");
   if (p->grid_blocks < 0) return fail(ctx, KH_EINVAL, "grid_blocks must be >= 0");
   if (p->waves_per_eu < 0 || p->waves_per_eu > 8) return fail(ctx, KH_EINVAL, "waves_per_eu must be in [0, 8]");
