@@ -110,6 +110,14 @@ def run_gpu(args):
     kern_ms = [a.elapsed_time(b) for a, b in evs]
     stats = ctx.kh_stats(st)
     log(f"timed {args.steps} steps: {wall:.3f} s; integrate kernel {np.mean(kern_ms):.2f} ms avg; stats {stats}")
+    # one more step outside the timed region, end to end: init, integrate and
+    # the copy of every final state and status to (pageable) host memory
+    torch.cuda.synchronize()
+    t_e = time.perf_counter()
+    ctx.kh_init_rays(kc, st)
+    ctx.kh_integrate(params, st)
+    ctx.kh_read_state(st)
+    e2e_s = time.perf_counter() - t_e
     flops, n_rhs, rhs_f, step_f = algorithmic_flops(K, stats, n, K.DOPRI5, K.RHS_FACTORED)
     ms_step = 1e3 * wall / args.steps
     kern_s = np.mean(kern_ms) / 1e3
@@ -133,6 +141,10 @@ def run_gpu(args):
                             "[-12,12], DOPRI5 rtol=atol=1e-8 FP64, 4 equatorial crossings",
                 "rays_per_step": n, "parallelism": "single GPU, persistent kernel"},
         rhs_evals_per_s=n_rhs * args.steps / wall,
+        useful_rhs_evals_per_s=(6 * stats["n_acc"] + n) * args.steps / wall,
+        end_to_end=dict(rays_per_s=n / e2e_s, ms=e2e_s * 1e3,
+                        includes="kh_init_rays + kh_integrate + kh_read_state of all 2^21 states and statuses "
+                                 "to pageable host memory (PCIe), one untimed-by-value step"),
         rhs_evals_per_step=n_rhs,
         accepted_steps_per_ray=stats["n_acc"] / n,
         rejected_steps_per_ray=stats["n_rej"] / n,

@@ -422,6 +422,29 @@ def test_out_of_range_tile_order_is_skipped(ctx):
     assert np.all(g["status"][64:192] != K.ACTIVE)
 
 
+def test_read_state_copies_ranges_to_the_host(ctx):
+    """kh_read_state: [count][8] host rows and statuses equal the device
+    arrays for the whole state, an inner range and a one-ray range; statuses
+    alone with host_s NULL; an empty range is a no-op; a range past the end
+    is refused."""
+    say("read state")
+    cam = W.Camera(0.9, 1000.0, 45.0, -12.0, 12.0, -12.0, 12.0, 37, 29)
+    st = gpu_image(ctx, [cam], K.kh_default_params())
+    s = st.s.cpu().numpy()
+    status = st.status.cpu().numpy()
+    for first, count in ((0, cam.n), (101, 517), (cam.n - 1, 1)):
+        hs, hst = ctx.kh_read_state(st, first, count)
+        assert np.array_equal(hs, s[:, first:first + count].T)
+        assert np.array_equal(hst, status[first:first + count])
+    only = np.full(50, -7, np.int32)
+    rc = K.lib().kh_read_state(ctx.handle, C.byref(st.c), 10, 50, None, only.ctypes.data, None)
+    assert rc == K.KH_OK and np.array_equal(only, status[10:60])
+    hs, hst = ctx.kh_read_state(st, 5, 0)
+    assert hs.shape == (0, 8) and hst.shape == (0,)
+    with pytest.raises(K.KerrHipError, match="range"):
+        ctx.kh_read_state(st, cam.n - 3, 4)
+
+
 def _is_permutation(perm, n):
     return perm.shape == (n,) and np.array_equal(np.sort(perm), np.arange(n))
 
