@@ -181,6 +181,69 @@ def test_image_kernel_full_size_sampled(ctx):
         assert np.array_equal(np.sort(listed), want)
 
 
+def test_pixel_init_targets_and_image_from_state(ctx):
+    """The surrogate pipeline's data calls on a ragged 23x19 camera:
+    kh_init_rays_pixels gives bitwise the kh_init_rays states of the listed
+    pixels; after integration, kh_image_from_state (in place and scattered
+    through a pixel list) and kh_mlp_targets equal their definitions
+    evaluated on the host from the state (first crossing, capture flag,
+    normalised targets, validity mask); kh_stats_device equals kh_stats."""
+    say("pixel init, targets, image from state")
+    cam = W.Camera(0.9, 1000.0, 45.0, -12.0, 12.0, -9.0, 9.0, 23, 19)
+    n = cam.n
+    kc = S.camera_struct(cam)
+    st = K.State(n, k_cross=1)
+    ctx.kh_init_rays([kc], st)
+    init_s = st.s.cpu().numpy()
+    pix = np.random.default_rng(5).permutation(n)[:200].astype(np.int32)
+    sp = K.State(len(pix), k_cross=1)
+    ctx.kh_init_rays_pixels(kc, torch.from_numpy(pix).cuda(), sp)
+    assert np.array_equal(sp.s.cpu().numpy(), init_s[:, pix])
+    ctx.kh_integrate(K.kh_default_params(k_cross=1), st)
+    torch.cuda.synchronize()
+    g = st.numpy()
+    cross = g["n_cross"] > 0
+    c0 = g["cross"][:, 0, :]
+    want_img = np.stack([np.where(cross, c0[:, 0], np.nan), np.where(cross, c0[:, 1], np.nan),
+                         np.where(cross, c0[:, 2], np.nan), (g["status"] == K.CAPTURED) * 1.0],
+                        axis=1).astype(np.float32)
+    out = torch.full((n, 4), -1.0, dtype=torch.float32, device="cuda")
+    ctx.kh_image_from_state(st, None, out)
+    assert np.array_equal(out.cpu().numpy(), want_img, equal_nan=True)
+    # scattered: state entry i goes to pixel rev[i]
+    rev = np.arange(n)[::-1].astype(np.int32).copy()
+    out2 = torch.full((n, 4), -1.0, dtype=torch.float32, device="cuda")
+    ctx.kh_image_from_state(st, torch.from_numpy(rev).cuda(), out2)
+    assert np.array_equal(out2.cpu().numpy()[rev], want_img, equal_nan=True)
+    # training targets
+    col, row = np.arange(n) % cam.width, np.arange(n) // cam.width
+    al = cam.alpha_min + (col + 0.5) * (cam.alpha_max - cam.alpha_min) / cam.width
+    be = cam.beta_min + (row + 0.5) * (cam.beta_max - cam.beta_min) / cam.height
+    f64 = dict(dtype=torch.float64, device="cuda")
+    x = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    t = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    mask = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ctx.kh_mlp_targets(st, torch.from_numpy(al).to(**f64), torch.from_numpy(be).to(**f64),
+                       torch.full((n,), cam.a, **f64), torch.full((n,), cam.incl, **f64), x, t, mask)
+    want_x = np.stack([al, be, np.full(n, cam.a), np.full(n, cam.incl)], axis=1).astype(np.float32)
+    assert np.array_equal(x.cpu().numpy(), want_x)
+    r, ph, gg = c0[:, 0], c0[:, 1], c0[:, 2]
+    rok = cross & (np.nan_to_num(r) > 0) & np.isfinite(r) & np.isfinite(ph)
+    gok = rok & np.isfinite(gg)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        want_t = np.stack([np.where(rok, (np.log(r) - 2) * 0.5, 0), np.where(rok, ph / np.pi, 0),
+                           np.where(gok, (gg - 0.8) / 0.3, 0), (g["status"] == K.CAPTURED) * 1.0], axis=1)
+    np.testing.assert_allclose(t.cpu().numpy(), want_t.astype(np.float32), rtol=1e-6, atol=1e-7)
+    assert np.array_equal(mask.cpu().numpy(), (rok * 1 + gok * 2).astype(np.uint8))
+    say(f"  {int(rok.sum())} rays with a crossing, {int(gok.sum())} with a finite redshift, "
+        f"{int((g['status'] == K.CAPTURED).sum())} captured")
+    assert rok.sum() > n // 4 and (g["status"] == K.CAPTURED).sum() > 0
+    dev = torch.zeros(8, dtype=torch.int64, device="cuda")
+    ctx.kh_stats_device(st, dev)
+    host = ctx.kh_stats(st)
+    assert dev.cpu().tolist() == host["status_counts"] + [host["n_acc"], host["n_rej"]]
+
+
 def test_forward_single_ray_and_one_past_a_block(ctx):
     p = S.init_params(13)
     net = K.Mlp(p, train=False)
