@@ -619,7 +619,10 @@ __global__ void k_finalize(KState S) {
 // ---------------------------------------------------------------------------
 // Initial data.
 // ---------------------------------------------------------------------------
-__device__ inline void finish_init(KState S, int64_t i, const double y[8], double a_phys, int kind, bool ok) {
+// cst: the constants of motion (E, L_z, Q, mu^2) in the chart, computed by the
+// caller, which also rates the geodesic for scheduling from them.
+__device__ inline void finish_init(KState S, int64_t i, const double y[8], double a_phys, int kind, bool ok,
+                                   const double cst[4]) {
   const int64_t n = S.n;
 #pragma unroll
   for (int c = 0; c < 8; ++c) S.s[c * n + i] = y[c];
@@ -635,8 +638,6 @@ __device__ inline void finish_init(KState S, int64_t i, const double y[8], doubl
   if (S.cross)
     for (int j = 0; j < 3 * S.k_cross; ++j) S.cross[i * 3 * S.k_cross + j] = __builtin_nan("");
   if (S.c0) {
-    double cst[4];
-    constants(kind == KH_NULL ? -a_phys : a_phys, y, y + 4, cst);
 #pragma unroll
     for (int q = 0; q < 4; ++q) S.c0[q * n + i] = cst[q];
   }
@@ -664,9 +665,7 @@ __device__ inline void camera_ray(double a_phys, double d, double incl, double a
 // root on a spherical photon orbit; the closer its minimum between the horizon
 // and r = 5 comes to zero, the more times the ray circles the hole.  The
 // minimum is bracketed on 17 radii and refined by three Newton steps on R'.
-__device__ inline int ray_priority(double a, const double y[8]) {
-  double cst[4];
-  constants(a, y, y + 4, cst);
+__device__ inline int ray_priority(double a, const double cst[4]) {
   const double E = cst[0];
   if (!(E > 0.0) || !(cst[1] == cst[1]) || !(cst[2] == cst[2])) return 0;
   const double xi = cst[1] / E, eta = cst[2] / (E * E);
@@ -704,9 +703,7 @@ __device__ inline int ray_priority(double a, const double y[8]) {
 // i.e. as A^{-3/2} with A = 1 / (2 (1 - E)) the semi-major axis of a Newtonian
 // orbit of the same binding energy.  16 keys per octave of A; unbound or
 // undefined energies get 0.
-__device__ inline int timelike_priority(double a, const double y[8]) {
-  double cst[4];
-  constants(a, y, y + 4, cst);
+__device__ inline int timelike_priority(const double cst[4]) {
   const double E = cst[0];
   if (!(E > 0.0 && E < 1.0)) return 0;
   const double A = 0.5 / (1.0 - E);
@@ -738,8 +735,10 @@ __global__ void k_init_rays(const kh_camera* cams, const int64_t* offs, int n_ca
     double y[8];
     bool ok;
     camera_ray(cam.a, cam.r_obs, cam.incl, al, be, y, &ok);
-    finish_init(S, i, y, cam.a, KH_NULL, ok);
-    if ((keys || gkeys) && ok) key = ray_priority(-cam.a, y);
+    double cst[4] = {0.0, 0.0, 0.0, 0.0};
+    if (S.c0 || keys || gkeys) constants(-cam.a, y, y + 4, cst);
+    finish_init(S, i, y, cam.a, KH_NULL, ok, cst);
+    if ((keys || gkeys) && ok) key = ray_priority(-cam.a, cst);
     if (gkeys) gkeys[i] = (uint8_t)key;
   }
   if (keys) {
@@ -855,7 +854,9 @@ __global__ void k_init_rays_pixels(kh_camera cam, const int32_t* pix, KState S) 
   double y[8];
   bool ok;
   camera_ray(cam.a, cam.r_obs, cam.incl, al, be, y, &ok);
-  finish_init(S, i, y, cam.a, KH_NULL, ok);
+  double cst[4] = {0.0, 0.0, 0.0, 0.0};
+  if (S.c0) constants(-cam.a, y, y + 4, cst);
+  finish_init(S, i, y, cam.a, KH_NULL, ok, cst);
 }
 
 __global__ void k_init_rays_list(const double* spin, const double* incl, const double* alpha, const double* beta,
@@ -865,8 +866,10 @@ __global__ void k_init_rays_list(const double* spin, const double* incl, const d
   double y[8];
   bool ok;
   camera_ray(spin[i], r_obs, incl[i], alpha[i], beta[i], y, &ok);
-  finish_init(S, i, y, spin[i], KH_NULL, ok);
-  if (gkeys) gkeys[i] = (uint8_t)(ok ? ray_priority(-spin[i], y) : 0);
+  double cst[4] = {0.0, 0.0, 0.0, 0.0};
+  if (S.c0 || gkeys) constants(-spin[i], y, y + 4, cst);
+  finish_init(S, i, y, spin[i], KH_NULL, ok, cst);
+  if (gkeys) gkeys[i] = (uint8_t)(ok ? ray_priority(-spin[i], cst) : 0);
 }
 
 __global__ void k_init_geodesics(int kind, const double* spin, const double* x3, const double* v3, KState S,
@@ -888,8 +891,11 @@ __global__ void k_init_geodesics(int kind, const double* spin, const double* x3,
     y[4] = null_k0(-a, y, y + 4, &ok);
   }
   ok = ok && (y[4] == y[4]);
-  finish_init(S, i, y, a, kind, ok);
-  if (gkeys) gkeys[i] = (uint8_t)(!ok ? 0 : (kind == KH_TIMELIKE ? timelike_priority(a, y) : ray_priority(-a, y)));
+  const double a_c = kind == KH_NULL ? -a : a;
+  double cst[4] = {0.0, 0.0, 0.0, 0.0};
+  if (S.c0 || gkeys) constants(a_c, y, y + 4, cst);
+  finish_init(S, i, y, a, kind, ok, cst);
+  if (gkeys) gkeys[i] = (uint8_t)(!ok ? 0 : (kind == KH_TIMELIKE ? timelike_priority(cst) : ray_priority(a_c, cst)));
 }
 
 // ---------------------------------------------------------------------------
