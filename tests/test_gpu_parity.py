@@ -481,6 +481,19 @@ def test_geodesic_schedule_orders_particles_longest_first(ctx):
     near_int = np.abs(kf - np.round(kf))[perm0] < 1e-9
     drops = np.diff(kh)
     assert np.all((drops <= 0) | near_int[1:] | near_int[:-1])
+    # resumed in calls of at most 500 accepted steps: bitwise the single run
+    st = K.State(n, schedule="geodesics")
+    ctx.kh_init_geodesics(K.TIMELIKE, t(pw["a"]), t(pw["x3"]), t(pw["v3"]), st)
+    calls = 0
+    while True:
+        ctx.kh_integrate(K.kh_default_params(t_end=1e4, r_escape=1e4, max_steps=500), st)
+        calls += 1
+        if ctx.kh_stats(st)["status_counts"][K.MAX_STEPS] == 0 or calls > 100:
+            break
+    c = st.numpy()
+    say(f"  resumed in {calls} calls")
+    for name in ("s", "status", "n_acc", "n_rej", "lam"):
+        assert np.array_equal(c[name], a[name], equal_nan=True), name
     cost = (a["n_acc"] + a["n_rej"]).astype(np.float64)[perm0]
     head, tail = cost[: n // 10].mean(), cost[-n // 10:].mean()
     say(f"  mean steps: first tenth of the schedule {head:.0f}, last tenth {tail:.0f}, max {cost.max():.0f}")
