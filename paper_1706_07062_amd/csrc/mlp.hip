@@ -118,6 +118,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 
   const f32x16 zero = {};
   f32x16 acc[2][4];
+  // The accumulators start from the layer's bias (per lane: outputs
+  // (2 w + tt) 32 + 8 g + 4 half + q of element 4 g + q), so the epilogue is
+  // SiLU and the BF16 store only.
+  auto bias_tiles = [&](const float* bias, f32x16 bt[2]) {
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const f32x4 b = *reinterpret_cast<const f32x4*>(bias + (2 * w + tt) * 32 + 8 * g + 4 * half);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bt[tt][4 * g + q] = b[q];
+      }
+  };
+  f32x16 bt[2];
+  bias_tiles(A.params + OFF_B[0], bt);
   // layer 0 (K = 4 padded to 16): the B operand of ray tile n is ray base + 32 n + r
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
@@ -141,7 +156,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     for (int tt = 0; tt < 2; ++tt) {
       const bf16x8 aw =
           *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[0] + ((2 * w + tt) * 32 + r) * KPAD[0] + 8 * half);
-      acc[tt][n] = mfma(aw, bx, zero);
+      acc[tt][n] = mfma(aw, bx, bt[tt]);
     }
   }
   for (int l = 0; l < 4; ++l) {
@@ -149,10 +164,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       const __bf16* wl = A.wb + (l == 1 ? OFF_WB[1] : l == 2 ? OFF_WB[2] : OFF_WB[3]);
       const __bf16* arow0 = wl + ((2 * w) * 32 + r) * HID + 8 * half;
       const __bf16* arow1 = arow0 + 32 * HID;
+      bias_tiles(A.params + (l == 1 ? OFF_B[1] : l == 2 ? OFF_B[2] : OFF_B[3]), bt);
 #pragma unroll
       for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) acc[tt][n] = zero;
+        for (int n = 0; n < 4; ++n) acc[tt][n] = bt[tt];
       bf16x8 a0 = *reinterpret_cast<const bf16x8*>(arow0);
       bf16x8 a1 = *reinterpret_cast<const bf16x8*>(arow1);
       for (int ks = 0; ks < HID / 16; ++ks) {
@@ -172,18 +188,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       }
       __syncthreads();  // every wave is done reading this layer's input rows
     }
-    const float* bias = A.params + (l == 0 ? OFF_B[0] : l == 1 ? OFF_B[1] : l == 2 ? OFF_B[2] : OFF_B[3]);
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt) {
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int m0 = (2 * w + tt) * 32 + 8 * g + 4 * half;
-        const f32x4 b = *reinterpret_cast<const f32x4*>(bias + m0);
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
           bf16x4 hv;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) hv[q] = (__bf16)silu(acc[tt][n][4 * g + q] + b[q]);
+          for (int q = 0; q < 4; ++q) hv[q] = (__bf16)silu(acc[tt][n][4 * g + q]);
           *reinterpret_cast<bf16x4*>(act + (32 * n + r) * LDA + m0) = hv;
         }
       }

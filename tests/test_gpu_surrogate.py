@@ -27,6 +27,19 @@ def ctx():
 rng = np.random.default_rng(1706070627)
 
 
+def _random_biases(p, seed):
+    """Every layer's bias set to N(0, 0.3) draws (the initialisation leaves
+    them zero), so the kernels' bias handling is exercised."""
+    q = p.copy()
+    g = np.random.default_rng(seed)
+    off = 0
+    for nin, nout in M.LAYERS:
+        off += nin * nout
+        q[off:off + nout] = g.normal(0.0, 0.3, nout)
+        off += nout
+    return q
+
+
 def _batch(n):
     x = np.stack([rng.uniform(-12, 12, n), rng.uniform(-12, 12, n), rng.uniform(0, 0.998, n),
                   np.radians(rng.uniform(5, 85, n))], axis=1).astype(np.float32)
@@ -37,12 +50,11 @@ def _batch(n):
 
 
 def test_forward_matches_reference(ctx):
-    """Raw outputs for 1000 rays (31 full waves and a ragged one) equal the FP64
-    reference with BF16 storage of weights and activations, to the FP32
-    accumulation-order level."""
+    """Raw outputs for 1000 rays (31 full waves and a ragged one), with
+    nonzero biases in every layer, equal the FP64 reference with BF16 storage
+    of weights and activations, to the FP32 accumulation-order level."""
     say("mlp forward")
-    p = S.init_params(11)
-    p[M.NPARAMS - 4:] = [0.1, -0.2, 0.3, 0.05]  # nonzero output bias
+    p = _random_biases(S.init_params(11), 21)
     net = K.Mlp(p, train=False)
     ctx.kh_mlp_sync(net)
     x, _, _ = _batch(1000)
@@ -63,7 +75,7 @@ def test_gradient_matches_reference(ctx):
     (BF16 storage of weights and activations; the GPU also stores the
     back-propagated errors as BF16)."""
     say("mlp gradient")
-    p = S.init_params(12) * 0.7
+    p = _random_biases(S.init_params(12) * 0.7, 23)
     net = K.Mlp(p, train=True)
     ctx.kh_mlp_sync(net)
     x, t, mask = _batch(512)
@@ -97,8 +109,7 @@ def test_image_kernel_decodes_forward_and_lists_fallback(ctx):
     reference with BF16 storage; and the fallback list is exactly the set of
     pixels whose capture probability lies in (tau, 1 - tau), in any order."""
     say("mlp image kernel")
-    p = S.init_params(12)
-    p[M.NPARAMS - 4:] = [0.2, -0.1, 0.05, 0.3]
+    p = _random_biases(S.init_params(12), 22)
     net = K.Mlp(p, train=False)
     ctx.kh_mlp_sync(net)
     cam = W.Camera(0.9, 1000.0, 45.0, -12.0, 12.0, -9.0, 9.0, 37, 23)
@@ -136,8 +147,7 @@ def test_image_kernel_full_size_sampled(ctx):
     fallback list holds exactly the pixels whose capture probability lies in
     (tau, 1 - tau), each once."""
     say("mlp image kernel, 4096^2")
-    p = S.init_params(14)
-    p[M.NPARAMS - 4:] = [0.1, 0.2, -0.1, 0.4]
+    p = _random_biases(S.init_params(14), 24)
     net = K.Mlp(p, train=False)
     ctx.kh_mlp_sync(net)
     cam = W.surrogate_eval_camera()
@@ -245,7 +255,7 @@ def test_pixel_init_targets_and_image_from_state(ctx):
 
 
 def test_forward_single_ray_and_one_past_a_block(ctx):
-    p = S.init_params(13)
+    p = _random_biases(S.init_params(13), 25)
     net = K.Mlp(p, train=False)
     ctx.kh_mlp_sync(net)
     x, _, _ = _batch(129)
