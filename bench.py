@@ -380,10 +380,11 @@ def particles_extra(ctx, K, W, torch):
         c0, c1 = st.c0.cpu().numpy(), st.c1.cpu().numpy()
         landed = st.status.cpu().numpy() == K.T_END
         drift = (np.abs(c1 - c0) / np.maximum(np.abs(c0), 1.0))[:, landed]
+        cnames = ("E", "Lz", "Q", "mu2")
         out[name] = dict(seconds=dt, particles_per_s=n / dt, steps_per_particle=s["n_acc"] / n,
                          status_counts=s["status_counts"],
-                         drift_median={k: float(np.median(drift[i])) for i, k in enumerate(("E", "Lz", "Q", "mu2"))},
-                         drift_p99={k: float(np.quantile(drift[i], 0.99)) for i, k in enumerate(("E", "Lz", "Q", "mu2"))})
+                         drift_median={k: float(np.median(drift[i])) for i, k in enumerate(cnames)},
+                         drift_p99={k: float(np.quantile(drift[i], 0.99)) for i, k in enumerate(cnames)})
         finals[name] = (st.s.cpu().numpy(), landed)
         log(f"particles {name}: {dt:.3f} s, {s['n_acc'] / n:.0f} steps/particle")
     (s64, l64), (s32, l32) = finals["fp64"], finals["fp32"]
