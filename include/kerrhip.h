@@ -94,7 +94,11 @@ typedef struct {
   int32_t *status;  /* [n]: KH_ACTIVE ... KH_FAILED */
   int32_t *n_acc;   /* [n]: accepted steps, cumulative over calls */
   int32_t *n_rej;   /* [n]: rejected DOPRI5 attempts, cumulative */
-  double *cross;    /* [n][k_cross][3] = (r, phi, g) of equatorial crossings, or NULL */
+  double *cross;    /* [n][k_cross][3] = (r, phi, g) of equatorial crossings, or NULL.  g = nu_obs / nu_em
+                       for an emitter on the Keplerian circular orbit about +z, Omega = 1/(r^{3/2} + a)
+                       with the physical spin a (prograde for a >= 0, retrograde for a < 0): g =
+                       1 / (u^t (1 - Omega xi)), xi = L_z / E of the photon; NaN where that orbit does
+                       not exist (r^{3/2} - 3 r^{1/2} + 2a <= 0) */
   int32_t *n_cross; /* [n]: crossings seen (may exceed k_cross), or NULL */
   int32_t k_cross;  /* 0..8 crossing slots per geodesic */
   double *c0;       /* [4][n] = (E, L_z, Q, mu^2) at initialisation, or NULL */

@@ -149,6 +149,32 @@ def test_kerr_ragged_image_dopri5_parity(ctx, incl):
     assert np.max(d[:, well]) < 1e-6
 
 
+@pytest.mark.parametrize("a, incl", [(1.0, 75.0), (-0.9, 40.0), (0.5, 90.0)])
+def test_extremal_negative_spin_and_edge_on_parity(ctx, a, incl):
+    """Edge cases of the geometry against the oracle, element by element: the
+    extremal hole a = 1 (degenerate horizon r_H = 1), a negative spin (hole
+    rotating about -z, so the chart spin flips sign), and an edge-on camera
+    (inclination 90 deg: the image plane contains the spin axis and every ray
+    starts in the equatorial plane's normal direction, z0 = beta).  41x29
+    images, DOPRI5 rtol 1e-8, two crossing slots."""
+    say(f"edge geometry a={a} incl={incl}")
+    cam = W.Camera(a, 1000.0, incl, -10, 10, -8, 8, 41, 29)
+    p = K.kh_default_params(k_cross=2)
+    g = gpu_image(ctx, [cam], p, k_cross=2).numpy()
+    o = oracle_image(cam, oracle_params(p))
+    rep = compare(g, o)
+    say(f"  {rep}")
+    well = ~o["ill"]
+    assert rep["status_mismatch"] == 0 and rep["n_pos_bad"] == 0
+    assert rep["ill"] < 0.02 * rep["n"]
+    assert np.sum(g["status"] == K.CAPTURED) > 20 and np.sum(g["status"] == K.ESCAPED) > 20
+    assert np.array_equal(g["n_cross"][well], o["n_cross"][well])
+    gc, oc = g["cross"][well], o["cross"][well]
+    both = ~np.isnan(oc)
+    assert np.array_equal(np.isnan(gc), np.isnan(oc))
+    assert np.max(np.abs(gc[both] - oc[both]) / np.maximum(np.abs(oc[both]), 1.0)) < POS_TOL
+
+
 def test_kerr_1024_both_inclinations_sampled(ctx):
     """The full workload (a = 0.99, 1024x1024 at 17 and 60 deg in one launch, the
     benchmark's launch configuration), checked on 600 pixels of each image."""

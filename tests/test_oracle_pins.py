@@ -487,6 +487,30 @@ def test_schwarzschild_crossings_match_orbit_equation():
     assert n_checked > 150 and n_multi >= 5
 
 
+def test_negative_spin_is_the_mirror_image():
+    """A hole of spin -a is the hole of spin a seen in a mirror: reflecting
+    y -> -y maps Kerr(a) to Kerr(-a) and the camera's alpha to -alpha (the
+    observer sits in the x-z plane).  So the a = -0.9 image equals the
+    a = 0.9 image with its columns reversed: same statuses and crossing
+    counts, final positions and crossing radii with y negated, crossing
+    azimuths negated.  (The redshift is not mirrored: its emitter orbits
+    about +z for either sign of the spin.)"""
+    W_, H = 31, 23
+    p = O.Params(method=O.DOPRI5, k_cross=2)
+    cols, rows = np.meshgrid(np.arange(W_), np.arange(H))
+    pix = (rows * W_ + cols).ravel()
+    mir = (rows * W_ + (W_ - 1 - cols)).ravel()
+    o1 = O.integrate(O.camera_rays(0.9, 1000.0, np.radians(40), -10, 10, -8, 8, W_, H, pix=pix), p)
+    o2 = O.integrate(O.camera_rays(-0.9, 1000.0, np.radians(40), -10, 10, -8, 8, W_, H, pix=mir), p)
+    assert np.array_equal(o1["status"], o2["status"])
+    assert np.array_equal(o1["n_cross"], o2["n_cross"])
+    flip = np.array([1, 1, -1, 1, 1, 1, -1, 1])[:, None]
+    np.testing.assert_allclose(o1["s"] * flip, o2["s"], rtol=1e-6, atol=1e-6 * 1000)
+    np.testing.assert_allclose(o1["cross"][..., 0], o2["cross"][..., 0], rtol=1e-8)
+    np.testing.assert_allclose(o1["cross"][..., 1], -o2["cross"][..., 1], rtol=1e-8, atol=1e-10)
+    assert np.sum(o1["status"] == O.CAPTURED) > 20
+
+
 def test_redshift_formula_matches_normalised_four_velocity():
     """The Keplerian u^t in the redshift equals the normalisation of
     u = u^t (1, Omega zhat x x) in the Cartesian metric (prograde, spin +a)."""
