@@ -240,7 +240,9 @@ kh_status kh_init_geodesics(kh_ctx *ctx, int32_t kind, const double *spin, const
  * terminates or takes max_steps accepted steps in this call.  Asynchronous; no
  * allocation and no host synchronisation.  Re-entrant: a paused state resumes
  * exactly (bitwise) where it stopped.  Persistent kernel: each 64-lane wave
- * takes rays from a global counter and refills retired lanes. */
+ * takes rays from a global counter and refills retired lanes, in the order of
+ * st->perm if set, else of st->order if set, else of the ray ids; the order
+ * changes the run time only, never a result. */
 kh_status kh_integrate(kh_ctx *ctx, const kh_params *p, kh_state *st, void *stream);
 
 /* Copy rays [first, first + count) to the host: host_s [count][8] (AoS, may be
