@@ -460,6 +460,41 @@ def cpu_baseline(args):
                        f"rtol 1e-8, {t_total:.1f} s wall")
 
 
+def precision_only(args):
+    """The benchmark images integrated in FP32 (rtol 1e-6), MIXED (rtol 1e-8)
+    and FP64 coordinate time, each `--steps` times after one untimed launch;
+    one JSON line of HIP-event times."""
+    import torch
+
+    import paper_1706_07062_amd as K
+    from paper_1706_07062_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    ctx = K.Context(0)
+    cams = W.kerr_1024()
+    kc = [K.kh_camera(c.a, c.r_obs, c.incl, c.alpha_min, c.alpha_max, c.beta_min, c.beta_max, c.width, c.height)
+          for c in cams]
+    st = K.State(sum(c.n for c in cams), k_cross=4)
+    res = {}
+    for name, prec, tol, method in (("fp32", K.P32, 1e-6, K.DOPRI5), ("mixed", K.PMIXED, 1e-8, K.DOPRI5),
+                                    ("coordinate_time_fp64", K.P64, 1e-8, K.DOPRI5_T)):
+        p = K.kh_default_params(k_cross=4, precision=prec, rtol=tol, atol=tol, method=method)
+        ms = []
+        for i in range(max(1, args.steps) + 1):
+            ctx.kh_init_rays(kc, st)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.kh_integrate(p, st)
+            e1.record()
+            torch.cuda.synchronize()
+            if i > 0:
+                ms.append(e0.elapsed_time(e1))
+        res[name] = dict(kernel_ms=ms, stats=ctx.kh_stats(st))
+        log(f"{name}: {np.mean(ms):.3f} ms")
+    print(json.dumps({"precision": res}), flush=True)
+    ctx.close()
+
+
 def surrogate_image_only():
     """The surrogate image kernel alone (timing and counters do not depend on
     the weights; the fallback count does)."""
@@ -496,6 +531,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, help="MiB; plain copy before the run (counter reference)")
     ap.add_argument("--surrogate-rays", type=int, default=10_000_000)
     ap.add_argument("--surrogate-steps", type=int, default=8000)
+    ap.add_argument("--precision-only", action="store_true",
+                    help="only the FP32, MIXED and coordinate-time launches on the benchmark images (for profilers)")
     ap.add_argument("--elapse-only", action="store_true",
                     help="only the fixed-step chart / layout comparison (Sec. 4's tab:elapse), for profilers")
     ap.add_argument("--surrogate-image-only", action="store_true",
@@ -509,6 +546,9 @@ def main():
         copy_probe(args.copy_probe)
     if args.surrogate_image_only:
         surrogate_image_only()
+        return
+    if args.precision_only:
+        precision_only(args)
         return
     if args.elapse_only:
         import torch
