@@ -246,7 +246,9 @@ kh_status kh_init_geodesics(kh_ctx *ctx, int32_t kind, const double *spin, const
 kh_status kh_integrate(kh_ctx *ctx, const kh_params *p, kh_state *st, void *stream);
 
 /* Copy rays [first, first + count) to the host: host_s [count][8] (AoS, may be
- * NULL), host_status [count] (may be NULL).  Synchronises the stream. */
+ * NULL), host_status [count] (may be NULL).  The rows are packed on the device
+ * in chunks of up to 2^20 rays, in context scratch of up to 64 MiB allocated
+ * on first use, and copied straight into host_s.  Synchronises the stream. */
 kh_status kh_read_state(kh_ctx *ctx, const kh_state *st, int64_t first, int64_t count, double *host_s,
                         int32_t *host_status, void *stream);
 

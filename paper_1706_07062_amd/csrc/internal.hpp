@@ -27,6 +27,8 @@ struct kh_ctx {
   uint8_t* d_gkeys = nullptr;  // per-geodesic scheduling keys (state.perm)
   int64_t gkeys_cap = 0;
   unsigned* d_perm_cnt = nullptr;  // 512 counters of the per-geodesic sort: counts, then next free position
+  double* d_stage = nullptr;       // kh_read_state: rows [chunk][8] packed on the device
+  int64_t stage_cap = 0;           // rows
   std::string err;
 };
 

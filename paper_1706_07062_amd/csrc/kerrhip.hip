@@ -16,7 +16,6 @@
 #include <cstring>
 #include <string>
 #include <type_traits>
-#include <vector>
 
 #include "kerrhip.h"
 #include "kerrhip_mlp.h"
@@ -839,6 +838,15 @@ __global__ void __launch_bounds__(kPermThreads) k_perm_scatter(const uint8_t* ke
   }
 }
 
+// Rows [count][8] of states first .. first + count - 1 (component-major in the
+// state) for one device-to-host copy.
+__global__ void k_pack_rows(const double* s, int64_t n, int64_t first, int64_t count, double* rows) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) rows[i * 8 + c] = s[c * n + first + i];
+}
+
 __global__ void k_perm_identity(int32_t* perm, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) perm[i] = (int32_t)i;
@@ -1187,6 +1195,7 @@ kh_status kh_destroy(kh_ctx* c) {
   if (c->d_keys) (void)hipFree(c->d_keys);
   if (c->d_gkeys) (void)hipFree(c->d_gkeys);
   if (c->d_perm_cnt) (void)hipFree(c->d_perm_cnt);
+  if (c->d_stage) (void)hipFree(c->d_stage);
   delete c;
   return KH_OK;
 }
@@ -1497,19 +1506,31 @@ kh_status kh_read_state(kh_ctx* ctx, const kh_state* st, int64_t first, int64_t 
   if (first < 0 || count < 0 || first + count > st->n) return fail(ctx, KH_EINVAL, "range outside the state");
   if ((s = set_device(ctx)) != KH_OK) return s;
   hipStream_t strm = (hipStream_t)stream;
-  std::vector<double> tmp;
   if (host_s && count > 0) {
-    tmp.resize(size_t(8) * count);
-    for (int c = 0; c < 8; ++c)
-      KH_HIP(ctx, hipMemcpyAsync(tmp.data() + size_t(c) * count, st->s + c * st->n + first, count * sizeof(double),
+    // Rows are packed on the device in chunks of at most 2^20 rays (64 MiB
+    // of context scratch) and copied straight into host_s.
+    const int64_t chunk = std::min<int64_t>(count, int64_t(1) << 20);
+    if (chunk > ctx->stage_cap) {
+      KH_HIP(ctx, hipStreamSynchronize(strm));
+      if (ctx->d_stage) KH_HIP(ctx, hipFree(ctx->d_stage));
+      ctx->d_stage = nullptr;
+      ctx->stage_cap = 0;
+      if (hipMalloc(&ctx->d_stage, (size_t)chunk * 8 * sizeof(double)) != hipSuccess)
+        return fail(ctx, KH_ENOMEM, "read-back staging buffer");
+      ctx->stage_cap = chunk;
+    }
+    for (int64_t off = 0; off < count; off += chunk) {
+      const int64_t m = std::min<int64_t>(chunk, count - off);
+      hipLaunchKernelGGL(k_pack_rows, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, strm, st->s, st->n,
+                         first + off, m, ctx->d_stage);
+      KH_HIP(ctx, hipGetLastError());
+      KH_HIP(ctx, hipMemcpyAsync(host_s + off * 8, ctx->d_stage, (size_t)m * 8 * sizeof(double),
                                  hipMemcpyDeviceToHost, strm));
+    }
   }
   if (host_status && count > 0)
     KH_HIP(ctx, hipMemcpyAsync(host_status, st->status + first, count * sizeof(int32_t), hipMemcpyDeviceToHost, strm));
   KH_HIP(ctx, hipStreamSynchronize(strm));
-  if (host_s)
-    for (int64_t i = 0; i < count; ++i)
-      for (int c = 0; c < 8; ++c) host_s[i * 8 + c] = tmp[size_t(c) * count + i];
   return KH_OK;
 }
 

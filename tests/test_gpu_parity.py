@@ -512,7 +512,8 @@ def test_read_state_copies_ranges_to_the_host(ctx):
     """kh_read_state: [count][8] host rows and statuses equal the device
     arrays for the whole state, an inner range and a one-ray range; statuses
     alone with host_s NULL; an empty range is a no-op; a range past the end
-    is refused."""
+    is refused; a state of more than 2^20 rays (two packing chunks) and a
+    range that starts near 2^20."""
     say("read state")
     cam = W.Camera(0.9, 1000.0, 45.0, -12.0, 12.0, -12.0, 12.0, 37, 29)
     st = gpu_image(ctx, [cam], K.kh_default_params())
@@ -529,6 +530,15 @@ def test_read_state_copies_ranges_to_the_host(ctx):
     assert hs.shape == (0, 8) and hst.shape == (0,)
     with pytest.raises(K.KerrHipError, match="range"):
         ctx.kh_read_state(st, cam.n - 3, 4)
+    # more rays than one 2^20-row chunk of the device-side packing
+    big = W.Camera(0.9, 1000.0, 45.0, -12.0, 12.0, -12.0, 12.0, 1025, 1024)
+    sb = K.State(big.n, constants=False)
+    ctx.kh_init_rays([kcam(big)], sb)
+    s = sb.s.cpu().numpy()
+    for first, count in ((0, big.n), ((1 << 20) - 5, 100)):
+        hs, hst = ctx.kh_read_state(sb, first, count)
+        assert np.array_equal(hs, s[:, first:first + count].T)
+        assert np.array_equal(hst, sb.status.cpu().numpy()[first:first + count])
 
 
 def _is_permutation(perm, n):
