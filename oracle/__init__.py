@@ -107,6 +107,10 @@ def lib():
         L.oracle_redshift.argtypes = [d, d, d]
         L.oracle_redshift.restype = d
         L.oracle_dopri5_sho.argtypes = [pd, d, i64, d, pd]
+        L.oracle_dopri5_sho_attempt.argtypes = [pd, d, d, d, pd, pd]
+        L.oracle_dopri5_sho_attempt.restype = d
+        L.oracle_controller_trace.argtypes = [P(_Params), d, i32, pd, i64, pd, pi32]
+        L.oracle_controller_trace.restype = i64
         L.oracle_bl_metric.argtypes = [d, pd, pd, pd]
         L.oracle_bl_rhs.argtypes = [d, pd, pd, pd]
         L.oracle_bl_constants.argtypes = [d, pd, pd, pd]
@@ -249,6 +253,30 @@ def dopri5_sho(y0, h, nsteps, rtol=1e-8):
     out = np.zeros(9)
     lib().oracle_dopri5_sho(_p(y0, C.c_double), h, nsteps, rtol, _p(out, C.c_double))
     return out[:8], out[8]
+
+
+def dopri5_sho_attempt(y0, h, rtol, atol):
+    """One Dormand-Prince attempt on y'' = -y: (y5, y4, error norm)."""
+    y0 = _f64(y0)
+    y5 = np.zeros(8)
+    y4 = np.zeros(8)
+    err = lib().oracle_dopri5_sho_attempt(_p(y0, C.c_double), h, rtol, atol, _p(y5, C.c_double),
+                                          _p(y4, C.c_double))
+    return y5, y4, err
+
+
+def controller_trace(params: Params, spin_phys: float, kind: int, y0, max_rec: int = 100000):
+    """Every Dormand-Prince attempt of one geodesic: rows (h, err, accepted,
+    r after the attempt, status after the attempt), and (status, accepted
+    steps, rejected attempts)."""
+    y0 = _f64(y0)
+    out = np.zeros((max_rec, 5))
+    res = np.zeros(3, np.int32)
+    m = lib().oracle_controller_trace(C.byref(params.c()), spin_phys, kind, _p(y0, C.c_double), max_rec,
+                                      _p(out, C.c_double), _p(res, C.c_int32))
+    if m < 0:
+        raise ValueError("oracle_controller_trace rejected its arguments")
+    return out[:m], tuple(int(v) for v in res)
 
 
 # ---------------------------------------------------------------------------

@@ -385,7 +385,24 @@ struct Ray {
   int32_t n_out = 0, j_out = 0;
   const double* t_out = nullptr;
   double* s_out = nullptr;
+  // optional record of every Dormand-Prince attempt (controller pins):
+  // kTraceFields values per attempt, at most trace_cap attempts
+  double* trace = nullptr;
+  int64_t trace_cap = 0, trace_len = 0;
 };
+
+// One record per attempt: the step tried, its error norm, 1 if accepted, the
+// radius of the state the next attempt starts from, and the status after it.
+constexpr int kTraceFields = 5;
+void trace_attempt(Ray& R, double h, double err, bool accepted, double r_next) {
+  if (!R.trace || R.trace_len >= R.trace_cap) return;
+  double* t = R.trace + kTraceFields * R.trace_len++;
+  t[0] = h;
+  t[1] = err;
+  t[2] = accepted ? 1.0 : 0.0;
+  t[3] = r_next;
+  t[4] = (double)R.status;
+}
 
 // First target at or after the entry time; a target equal to it takes the
 // entry state.
@@ -492,7 +509,7 @@ const double S1 = 5179.0 / 57600, S3 = 7571.0 / 16695, S4 = 393.0 / 640, S5 = -9
 // 5th-order solution y5, its derivative f7 (FSAL) and the RMS error norm.
 template <class RHS>
 double dopri5_attempt(RHS&& F, const double y[8], const double f1[8], double h, double rtol, double atol,
-                      double y5[8], double f7[8]) {
+                      double y5[8], double f7[8], double* y4_out = nullptr) {
   double f2[8], f3[8], f4[8], f5[8], f6[8], t[8];
   for (int c = 0; c < 8; ++c) t[c] = y[c] + h * (A21 * f1[c]);
   F(t, f2);
@@ -510,6 +527,7 @@ double dopri5_attempt(RHS&& F, const double y[8], const double f1[8], double h, 
   double s = 0.0;
   for (int c = 0; c < 8; ++c) {
     double y4 = y[c] + h * (S1 * f1[c] + S3 * f3[c] + S4 * f4[c] + S5 * f5[c] + S6 * f6[c] + S7 * f7[c]);
+    if (y4_out) y4_out[c] = y4;
     double sc = atol + rtol * std::max(std::fabs(y[c]), std::fabs(y5[c]));
     double e = (y5[c] - y4) / sc;
     s += e * e;
@@ -542,6 +560,8 @@ void run_dopri5(const oracle_params& p, const Geo& G, Ray& R) {
     double y5[8], f7[8];
     double err = dopri5_attempt(F, R.y, f1, h, p.rtol, p.atol, y5, f7);
     ++attempts;
+    const double h_try = h;
+    auto traced = [&]() { trace_attempt(R, h_try, err, err <= 1.0, radius(a, R.y)); };
     if (err <= 1.0) {
       double y0[8], f0[8];
       std::memcpy(y0, R.y, sizeof y0);
@@ -553,6 +573,7 @@ void run_dopri5(const oracle_params& p, const Geo& G, Ray& R) {
       ++steps;
       if (any_nan(R.y)) {
         R.status = ST_FAILED;
+        traced();
         return;
       }
       if (p.k_cross > 0) {
@@ -582,6 +603,7 @@ void run_dopri5(const oracle_params& p, const Geo& G, Ray& R) {
       }
       if (st != ST_ACTIVE) {
         R.status = st;
+        traced();
         return;
       }
       h *= grow_factor(err, after_reject);
@@ -589,6 +611,7 @@ void run_dopri5(const oracle_params& p, const Geo& G, Ray& R) {
       after_reject = false;
       if (steps >= p.max_steps) {
         R.status = ST_MAX_STEPS;
+        traced();
         return;
       }
     } else {
@@ -597,13 +620,13 @@ void run_dopri5(const oracle_params& p, const Geo& G, Ray& R) {
       after_reject = true;
       if (!(h >= 1e-12 * p.h_coeff * hscale(G.kind, radius(a, R.y)))) {  // also ends a NaN step
         R.status = ST_FAILED;
+        traced();
         return;
       }
     }
-    if (attempts > 4 * p.max_steps + 1000) {
-      R.status = ST_MAX_STEPS;
-      return;
-    }
+    if (attempts > 4 * p.max_steps + 1000) R.status = ST_MAX_STEPS;
+    traced();
+    if (R.status != ST_ACTIVE) return;
   }
 }
 
@@ -1088,6 +1111,53 @@ void oracle_dopri5_sho(const double y0[8], double h, int64_t nsteps, double rtol
   }
   std::memcpy(out, y, sizeof y);
   out[8] = err;
+}
+
+// One Dormand-Prince attempt of step h on y'' = -y (the same 8-component
+// layout as above) with separate tolerances: the 5th-order solution y5, the
+// embedded 4th-order solution y4 and the error norm; returns the norm.
+double oracle_dopri5_sho_attempt(const double y0[8], double h, double rtol, double atol, double y5[8],
+                                 double y4[8]) {
+  auto F = [](const double* y, double* dy) {
+    for (int c = 0; c < 4; ++c) {
+      dy[c] = y[4 + c];
+      dy[4 + c] = -y[c];
+    }
+  };
+  double f1[8], f7[8];
+  F(y0, f1);
+  return dopri5_attempt(F, y0, f1, h, rtol, atol, y5, f7, y4);
+}
+
+// One geodesic (chart spin from the physical spin and the kind, as in
+// oracle_integrate) integrated by the Dormand-Prince integrator, recording
+// every attempt in out[max_rec][5] = (h, err, accepted, r after the attempt,
+// status after the attempt).  res[0..2] = (status, accepted steps, rejected
+// attempts).  Returns the number of records.
+int64_t oracle_controller_trace(const oracle_params* p, double spin_phys, int32_t kind, const double y0[8],
+                                int64_t max_rec, double* out, int32_t* res) {
+  if (!p || p->method != M_DOPRI5 || max_rec < 0) return -1;
+  Geo G;
+  G.kind = kind;
+  G.a_phys = spin_phys;
+  G.a_chart = (kind == KIND_NULL) ? -spin_phys : spin_phys;
+  Ray R;
+  std::memcpy(R.y, y0, sizeof R.y);
+  R.lam = 0.0;
+  R.phi = std::atan2(R.y[2], R.y[1]);
+  R.status = ST_ACTIVE;
+  R.nacc = R.nrej = R.ncross = 0;
+  std::vector<double> cbuf(3 * std::max(p->k_cross, 1), NAN);
+  R.cross = cbuf.data();
+  R.trace = out;
+  R.trace_cap = max_rec;
+  run_dopri5(*p, G, R);
+  if (res) {
+    res[0] = R.status;
+    res[1] = R.nacc;
+    res[2] = R.nrej;
+  }
+  return R.trace_len;
 }
 
 }  // extern "C"
