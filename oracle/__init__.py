@@ -81,6 +81,13 @@ class Params:
 _lib = None
 
 
+def default_threads() -> int:
+    """Host threads for the oracle's pool: the CPUs this process may run on,
+    at most 16."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(16, n))
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -188,6 +195,7 @@ def integrate(init: dict, params: Params, nthreads: int = 0, t_out=None) -> dict
     c0 = np.zeros((4, n))
     c1 = np.zeros((4, n))
     cp = params.c()
+    nthreads = nthreads or default_threads()
     t_out = np.zeros(0) if t_out is None else _f64(t_out)
     n_out = len(t_out)
     s_out = np.full((n, max(n_out, 1), 8), np.nan)
@@ -336,5 +344,5 @@ def rk4_fixed(chart, a, h_coeff, r_stop, r_escape, nsteps, s, status=None, steps
     st = np.zeros(n, np.int32) if status is None else np.array(status, dtype=np.int32)
     sp = np.zeros(n, np.int32) if steps is None else np.array(steps, dtype=np.int32)
     lib().oracle_rk4_fixed(CHARTS[chart], a, h_coeff, r_stop, r_escape, nsteps, n, _p(y, C.c_double),
-                           _p(st, C.c_int32), _p(sp, C.c_int32), nthreads)
+                           _p(st, C.c_int32), _p(sp, C.c_int32), nthreads or default_threads())
     return np.ascontiguousarray(y.T), st, sp

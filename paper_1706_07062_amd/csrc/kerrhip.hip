@@ -47,21 +47,18 @@ __device__ inline double r_horizon(double a) { return 1.0 + ksqrt(1.0 - a * a); 
 // 0.9 err^{-1/5} to [0.2, 5], which only needs q in [3.5e-8, 3.5e6]; q is held
 // to [1e-10, 1e8] (a NaN becomes 1e-10: callers test for it first), which
 // keeps every clamp decision.  An FP32 estimate from the hardware log2 / exp2
-// (relative error ~1e-6) is refined by two Newton steps on y^{-10} = q,
-// y <- y + y (1 - q y^10) / 10, each of which takes the relative error e to
-// about 5.5 e^2: full double precision up to a few ulps, in 17 instructions
-// instead of the ~200 of a general FP64 pow.
+// (relative error below 5e-7 on that range) is refined by one Newton step on
+// y^{-10} = q, y <- y + y (1 - q y^10) / 10, which takes the relative error e
+// to about 5.5 e^2 < 2e-12: the step factor is then within 2e-12 of the exact
+// power, far below anything that moves a step (the accept decision uses q
+// itself), in 10 instructions instead of the ~200 of a general FP64 pow.
 __device__ inline double kpow_m1_10(double q) {
   q = q > 1e-10 ? q : 1e-10;
   q = q < 1e8 ? q : 1e8;
-  double y = (double)__builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf((float)q));
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double y2 = y * y, y5 = y2 * y2 * y;
-    const double t = fma(-q, y5 * y5, 1.0);
-    y = fma(0.1 * y, t, y);
-  }
-  return y;
+  const double y = (double)__builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf((float)q));
+  const double y2 = y * y, y5 = y2 * y2 * y;
+  const double t = fma(-q, y5 * y5, 1.0);
+  return fma(0.1 * y, t, y);
 }
 __device__ inline float kpow_m1_10(float q) {
   q = q > 1e-10f ? q : 1e-10f;
@@ -439,7 +436,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
           const TS rtol = (TS)P.rtol, atol = (TS)P.atol;
           TS err2;  // squared RMS error norm
           if (PREC == KH_PMIXED && __ballot(r_cur < (TS)P.r_fp64) == 0ull)
-            err2 = dp5_attempt<FORM, TS, TF, CT>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
+            err2 = dp5_attempt<FORM, TS, TF, CT, TF>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
           else
             err2 = dp5_attempt<FORM, TS, TS, CT>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
 
@@ -1049,35 +1046,40 @@ thread_local bool g_skip_ptr_query = false;  // set per entry point while its st
 
 bool device_ok(const void* p) { return g_skip_ptr_query ? p != nullptr : is_device_ptr(p); }
 
-kh_status check_state(kh_ctx* ctx, const kh_state* st, bool need_cross) {
-  if (!st) return fail(ctx, KH_EINVAL, "state is NULL");
-  if (st->n < 1 || st->n >= (int64_t(1) << 31)) return fail(ctx, KH_EINVAL, "state.n must be in [1, 2^31)");
-  if (st->k_cross < 0 || st->k_cross > 8) return fail(ctx, KH_EINVAL, "state.k_cross must be in [0, 8]");
+const char* state_problem(const kh_state* st, bool need_cross) {
+  if (!st) return "state is NULL";
+  if (st->n < 1 || st->n >= (int64_t(1) << 31)) return "state.n must be in [1, 2^31)";
+  if (st->k_cross < 0 || st->k_cross > 8) return "state.k_cross must be in [0, 8]";
   const void* d8[] = {st->s, st->spin, st->h, st->lam, st->phi};
   for (const void* p : d8)
     if (!p || !aligned(p, 8) || !device_ok(p))
-      return fail(ctx, KH_EINVAL, "state arrays s, spin, h, lam, phi must be 8-byte aligned device memory");
+      return "state arrays s, spin, h, lam, phi must be 8-byte aligned device memory";
   const void* d4[] = {st->kind, st->status, st->n_acc, st->n_rej};
   for (const void* p : d4)
     if (!p || !aligned(p, 4) || !device_ok(p))
-      return fail(ctx, KH_EINVAL, "state arrays kind, status, n_acc, n_rej must be 4-byte aligned device memory");
+      return "state arrays kind, status, n_acc, n_rej must be 4-byte aligned device memory";
   const void* opt8[] = {st->c0, st->c1, st->cross};
   for (const void* p : opt8)
     if (p && (!aligned(p, 8) || !device_ok(p)))
-      return fail(ctx, KH_EINVAL, "state arrays c0, c1, cross must be NULL or 8-byte aligned device memory");
+      return "state arrays c0, c1, cross must be NULL or 8-byte aligned device memory";
   if (st->n_cross && (!aligned(st->n_cross, 4) || !device_ok(st->n_cross)))
-    return fail(ctx, KH_EINVAL, "state.n_cross must be NULL or 4-byte aligned device memory");
+    return "state.n_cross must be NULL or 4-byte aligned device memory";
   if (st->order && (!aligned(st->order, 4) || !device_ok(st->order)))
-    return fail(ctx, KH_EINVAL, "state.order must be NULL or 4-byte aligned device memory");
+    return "state.order must be NULL or 4-byte aligned device memory";
   if (st->perm && (!aligned(st->perm, 4) || !device_ok(st->perm)))
-    return fail(ctx, KH_EINVAL, "state.perm must be NULL or 4-byte aligned device memory");
-  if (st->n_out < 0) return fail(ctx, KH_EINVAL, "state.n_out must be >= 0");
+    return "state.perm must be NULL or 4-byte aligned device memory";
+  if (st->n_out < 0) return "state.n_out must be >= 0";
   if (st->n_out > 0 && (!st->t_out || !st->s_out || !aligned(st->t_out, 8) || !aligned(st->s_out, 8) ||
                         !device_ok(st->t_out) || !device_ok(st->s_out)))
-    return fail(ctx, KH_EINVAL, "state.n_out > 0 needs t_out and s_out in 8-byte aligned device memory");
+    return "state.n_out > 0 needs t_out and s_out in 8-byte aligned device memory";
   if (need_cross && st->k_cross > 0 && (!st->cross || !st->n_cross))
-    return fail(ctx, KH_EINVAL, "state.k_cross > 0 requires cross and n_cross");
-  return KH_OK;
+    return "state.k_cross > 0 requires cross and n_cross";
+  return nullptr;
+}
+
+kh_status check_state(kh_ctx* ctx, const kh_state* st, bool need_cross) {
+  const char* m = state_problem(st, need_cross);
+  return m ? fail(ctx, KH_EINVAL, m) : KH_OK;
 }
 
 kh_status set_device(kh_ctx* ctx) {
@@ -1414,38 +1416,72 @@ kh_status kh_init_geodesics(kh_ctx* ctx, int32_t kind, const double* spin, const
   return gkeys ? sort_perm(ctx, st, gkeys, (hipStream_t)stream) : KH_OK;
 }
 
-kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stream) {
-  if (!ctx) return KH_EINVAL;
-  g_skip_ptr_query = capturing(stream);
-  if (!p) return fail(ctx, KH_EINVAL, "params is NULL");
-  if (p->method != KH_RK4 && p->method != KH_DOPRI5 && p->method != KH_DOPRI5_T)
-    return fail(ctx, KH_EINVAL, "unknown method");
-  if (p->precision != KH_P64 && p->precision != KH_P32 && p->precision != KH_PMIXED)
-    return fail(ctx, KH_EINVAL, "unknown precision");
-  if (p->rhs_form != KH_RHS_FACTORED && p->rhs_form != KH_RHS_PAPER) return fail(ctx, KH_EINVAL, "unknown rhs_form");
-  if (!(p->h_coeff > 0.0) || !(p->r_h_factor > 0.0) || !(p->r_escape > 0.0) || p->max_steps < 1)
-    return fail(ctx, KH_EINVAL, "need h_coeff, r_h_factor, r_escape > 0 and max_steps >= 1");
-  if (p->method != KH_RK4 && (!(p->rtol > 0.0) || !(p->atol > 0.0) || !(p->hmax_coeff > 0.0)))
-    return fail(ctx, KH_EINVAL, "DOPRI5 needs rtol, atol, hmax_coeff > 0");
-  if (p->k_cross < 0 || p->k_cross > 8) return fail(ctx, KH_EINVAL, "k_cross must be in [0, 8]");
-  if (p->method == KH_RK4 && (p->k_cross > 0 || p->t_end > 0.0 || (st && st->n_out > 0)))
-    return fail(ctx, KH_EUNSUPPORTED, "crossings, t_end and dense output need a DOPRI5 method");
-  if (p->k_cross > 0 && p->t_end > 0.0)
-    return fail(ctx, KH_EUNSUPPORTED, "crossing records and t_end landing are not combined");
-  if (p->rhs_form == KH_RHS_PAPER && p->precision == KH_PMIXED)
-    return fail(ctx, KH_EUNSUPPORTED, "the paper-form right-hand side is built for P64 and P32 only");
-  const int block = p->block_size ? p->block_size : 256;
-  if (block < 64 || block > 256 || block % 64) return fail(ctx, KH_EINVAL, "block_size must be 64, 128, 192 or 256");
-  const int refill = p->refill_min ? p->refill_min : 12;
-  if (refill < 1 || refill > 64) return fail(ctx, KH_EINVAL, "refill_min must be in [1, 64]");
-  if (p->grid_blocks < 0) return fail(ctx, KH_EINVAL, "grid_blocks must be >= 0");
-  if (p->waves_per_eu < 0 || p->waves_per_eu > 8) return fail(ctx, KH_EINVAL, "waves_per_eu must be in [0, 8]");
-  if (p->queue_parts < 0 || p->queue_parts > kParts) return fail(ctx, KH_EINVAL, "queue_parts must be in [0, 8]");
-  kh_status s = check_state(ctx, st, p->k_cross > 0);
-  if (s != KH_OK) return s;
-  if (p->k_cross > st->k_cross) return fail(ctx, KH_EINVAL, "params.k_cross exceeds state.k_cross");
-  if ((s = set_device(ctx)) != KH_OK) return s;
+}  // extern "C"
 
+namespace {
+
+// Argument checks of kh_integrate that need no context: nullptr when the
+// parameters are usable, else the message (and *code the status).
+const char* params_problem(const kh_params* p, const kh_state* st, kh_status* code) {
+  *code = KH_EINVAL;
+  if (!p) return "params is NULL";
+  if (p->method != KH_RK4 && p->method != KH_DOPRI5 && p->method != KH_DOPRI5_T) return "unknown method";
+  if (p->precision != KH_P64 && p->precision != KH_P32 && p->precision != KH_PMIXED) return "unknown precision";
+  if (p->rhs_form != KH_RHS_FACTORED && p->rhs_form != KH_RHS_PAPER) return "unknown rhs_form";
+  if (!(p->h_coeff > 0.0) || !(p->r_h_factor > 0.0) || !(p->r_escape > 0.0) || p->max_steps < 1)
+    return "need h_coeff, r_h_factor, r_escape > 0 and max_steps >= 1";
+  if (p->method != KH_RK4 && (!(p->rtol > 0.0) || !(p->atol > 0.0) || !(p->hmax_coeff > 0.0)))
+    return "DOPRI5 needs rtol, atol, hmax_coeff > 0";
+  if (p->k_cross < 0 || p->k_cross > 8) return "k_cross must be in [0, 8]";
+  if (p->method == KH_RK4 && (p->k_cross > 0 || p->t_end > 0.0 || (st && st->n_out > 0))) {
+    *code = KH_EUNSUPPORTED;
+    return "crossings, t_end and dense output need a DOPRI5 method";
+  }
+  if (p->k_cross > 0 && p->t_end > 0.0) {
+    *code = KH_EUNSUPPORTED;
+    return "crossing records and t_end landing are not combined";
+  }
+  if (p->rhs_form == KH_RHS_PAPER && p->precision == KH_PMIXED) {
+    *code = KH_EUNSUPPORTED;
+    return "the paper-form right-hand side is built for P64 and P32 only";
+  }
+  const int block = p->block_size ? p->block_size : 256;
+  if (block < 64 || block > 256 || block % 64) return "block_size must be 64, 128, 192 or 256";
+  const int refill = p->refill_min ? p->refill_min : 12;
+  if (refill < 1 || refill > 64) return "refill_min must be in [1, 64]";
+  if (p->grid_blocks < 0) return "grid_blocks must be >= 0";
+  if (p->waves_per_eu < 0 || p->waves_per_eu > 8) return "waves_per_eu must be in [0, 8]";
+  if (p->queue_parts < 0 || p->queue_parts > kParts) return "queue_parts must be in [0, 8]";
+  if (const char* m = state_problem(st, p->k_cross > 0)) return m;
+  if (p->k_cross > st->k_cross) return "params.k_cross exceeds state.k_cross";
+  *code = KH_OK;
+  return nullptr;
+}
+
+// Text of the last HIP failure of a launch below (per host thread; no allocation).
+thread_local char g_hip_msg[256];
+
+const char* hip_msg(hipError_t e, const char* where) {
+  std::snprintf(g_hip_msg, sizeof g_hip_msg, "%s: %s", where, hipGetErrorString(e));
+  return g_hip_msg;
+}
+
+#define KH_TRY(call)                                          \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) {                                   \
+      *msg = hip_msg(e_, #call);                              \
+      return KH_EHIP;                                         \
+    }                                                         \
+  } while (0)
+
+// The launches of an integrate call, after the argument checks, with the
+// work-queue counters `q` (at least kParts of them, device memory) on the
+// current device of `n_cu` compute units: counter reset, the persistent
+// integrate kernel, the finalize pass.  No allocation, no synchronisation.
+kh_status launch_integrate(const kh_params* p, const kh_state* st, hipStream_t strm, unsigned long long* q, int n_cu,
+                           const char** msg) {
+  const int block = p->block_size ? p->block_size : 256;
   KParams kp;
   kp.h_coeff = p->h_coeff;
   kp.rtol = p->rtol;
@@ -1463,7 +1499,7 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   kp.max_steps = (int32_t)std::min<int64_t>(p->max_steps, INT32_MAX);
   kp.max_tries = (int32_t)std::min<int64_t>(4 * std::min<int64_t>(p->max_steps, INT32_MAX) + 1000, INT32_MAX);
   kp.k_cross = p->k_cross;
-  kp.refill_min = refill;
+  kp.refill_min = p->refill_min ? p->refill_min : 12;
   kp.parts = p->queue_parts ? p->queue_parts : kParts;
 
   // Default register budget: MIXED DOPRI5 runs faster at three waves per SIMD
@@ -1471,30 +1507,47 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   int wpe = p->waves_per_eu;
   if (wpe == 0) wpe = (p->method != KH_RK4 && p->precision == KH_PMIXED && p->rhs_form == KH_RHS_FACTORED) ? 3 : 1;
   void* fn = pick_kernel(p->method, p->precision, p->rhs_form, wpe, st->n_out > 0);
-  if (!fn) return fail(ctx, KH_EUNSUPPORTED, "no kernel for this method / precision / rhs_form / waves_per_eu");
+  if (!fn) {
+    *msg = "no kernel for this method / precision / rhs_form / waves_per_eu";
+    return KH_EUNSUPPORTED;
+  }
   // dynamic LDS: one crossing queue (kQFields x kQCap doubles + a counter) per wave
   const size_t lds = p->k_cross > 0 ? (size_t)(block / 64) * (kQFields * kQCap + 1) * sizeof(double) : 0;
   int grid = p->grid_blocks;
   if (grid == 0) {
     int per_cu = 0;
-    KH_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, block, lds));
-    grid = std::max(1, per_cu) * ctx->n_cu;
+    KH_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, block, lds));
+    grid = std::max(1, per_cu) * n_cu;
   }
   const int64_t need = (st->n + block - 1) / block;
   if (grid > need) grid = (int)need;
-  hipStream_t strm = (hipStream_t)stream;
-  unsigned long long* q = ctx->d_queue;
   hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, strm, q, kParts);
-  KH_HIP(ctx, hipGetLastError());
+  KH_TRY(hipGetLastError());
   const KState ks = to_k(st);
   void* args[] = {(void*)&kp, (void*)&ks, (void*)&q};
-  KH_HIP(ctx, hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, strm));
-  {
-    const int b = 256;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((st->n + b - 1) / b)), dim3(b), 0, strm, ks);
-    KH_HIP(ctx, hipGetLastError());
-  }
+  KH_TRY(hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, strm));
+  const int b = 256;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((st->n + b - 1) / b)), dim3(b), 0, strm, ks);
+  KH_TRY(hipGetLastError());
   return KH_OK;
+}
+
+#undef KH_TRY
+
+}  // namespace
+
+extern "C" {
+
+kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stream) {
+  if (!ctx) return KH_EINVAL;
+  g_skip_ptr_query = capturing(stream);
+  kh_status code;
+  if (const char* m = params_problem(p, st, &code)) return fail(ctx, code, m);
+  kh_status s;
+  if ((s = set_device(ctx)) != KH_OK) return s;
+  const char* msg = nullptr;
+  s = launch_integrate(p, st, (hipStream_t)stream, ctx->d_queue, ctx->n_cu, &msg);
+  return s == KH_OK ? KH_OK : fail(ctx, s, msg ? msg : "kh_integrate");
 }
 
 kh_status kh_read_state(kh_ctx* ctx, const kh_state* st, int64_t first, int64_t count, double* host_s,

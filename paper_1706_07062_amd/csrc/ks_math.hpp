@@ -67,9 +67,20 @@ __host__ __device__ inline float krsqrt(float x) {
 // Reciprocal for the scales of the error norm (same accuracy as krcp).
 __host__ __device__ inline double krcp_est(double x) { return krcp(x); }
 __host__ __device__ inline float krcp_est(float x) { return krcp(x); }
-// sqrt(x) = x / sqrt(x) for x >= 0, without a branch: the argument of the
-// reciprocal square root is kept >= 1e-300 (1e-30 in FP32), so x = 0 gives 0.
-__host__ __device__ inline double ksqrt(double x) { return x * krsqrt(x > 1e-300 ? x : 1e-300); }
+// sqrt(x) for x >= 0, without a branch: the argument of the reciprocal square
+// root is kept >= 1e-300 (1e-30 in FP32), so x = 0 gives 0.  On the device
+// the Newton-Raphson step is taken on s = x y (y the rsq estimate) itself:
+// e = 1 - s y, s <- s + s e / 2, which squares the relative error as the step
+// on y does, in one instruction less.
+__host__ __device__ inline double ksqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(x > 1e-300 ? x : 1e-300);
+  const double s = x * y;
+  return fma(0.5 * s, fma(-s, y, 1.0), s);
+#else
+  return x * krsqrt(x > 1e-300 ? x : 1e-300);
+#endif
+}
 __host__ __device__ inline float ksqrt(float x) { return x * krsqrt(x > 1e-30f ? x : 1e-30f); }
 
 // Azimuth estimate with |error| < 0.08 rad, enough to recover a winding count
@@ -96,15 +107,27 @@ struct Accel {
   T rdot;  // dr / dlambda = d_j r k^j
 };
 
+// Keeps the compiler from evaluating a rarely taken branch unconditionally
+// (if-conversion would run its reciprocal on every call).
+__host__ __device__ inline void kh_keep_branch() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" ::: "memory");
+#endif
+}
+
 // Radius from eq:CKSr.  Both root formulas are exact; the second avoids
-// cancellation when R^2 < a^2.
+// cancellation when R^2 < a^2 and is a real branch (taken only inside r < a).
 template <typename T>
 __host__ __device__ inline T ks_r2(T a2, T X, T Y, T Z) {
   const T z2 = Z * Z;
-  const T w = X * X + Y * Y + z2 - a2;
+  const T w = X * X + (Y * Y + (z2 - a2));
   const T q = ksqrt(w * w + T(4) * a2 * z2);
-  if (w >= T(0)) return T(0.5) * (w + q);
-  return T(2) * a2 * z2 * krcp(q - w);  // only inside r < a
+  T r2 = T(0.5) * (w + q);
+  if (!(w >= T(0))) {
+    kh_keep_branch();
+    r2 = T(2) * a2 * z2 * krcp(q - w);
+  }
+  return r2;
 }
 
 // The paper's regrouped form, written out with its 12 temporaries.
@@ -193,16 +216,17 @@ __host__ __device__ inline Accel<T> rhs_factored(T a, const T x[4], const T k[4]
   const T S = r2 + a2, D = r2 * r2 + a2z2;
   const T iSD = krcp(S * D);
   const T iS = D * iSD, iD = S * iSD;
-  const T r3 = r2 * r;
-  const T f = T(2) * r3 * iD;
   const T rS = r * iS, aS = a * iS;
   const T l1 = rS * X + aS * Y, l2 = rS * Y - aS * X, l3 = Z * ir;
-  // gradient of r, and of f = m d_j r - cz delta_jz
+  // gradient of r, and of f = m d_j r - cz delta_jz: with c = r / D,
+  // f = 2 r^3 / D = 2 c r^2 and d_j f = f (3 / r - 4 r^3 / D) d_j r - 2 f a^2 z / D
+  // delta_jz, where 4 r^3 / D = 2 f
   const T c = r * iD;
   const T cr2 = c * r2;
+  const T f = cr2 + cr2;
   const T dr1 = cr2 * X, dr2 = cr2 * Y, dr3 = c * S * Z;
-  const T m = f * (T(3) * ir - T(4) * r3 * iD);
-  const T cz = T(2) * f * a2 * Z * iD;
+  const T m = f * (T(3) * ir - T(2) * f);
+  const T cz = (f * iD) * (T(2) * a2 * Z);
   // p of the Jacobian's rank-one part
   const T px = (X - T(2) * r * l1) * iS;
   const T py = (Y - T(2) * r * l2) * iS;

@@ -13,6 +13,8 @@
 // coefficients A A, b A and e A (e = b - b*) are folded at compile time.
 #pragma once
 
+#include <type_traits>
+
 #include "bl_math.hpp"
 #include "ks_math.hpp"
 
@@ -31,8 +33,10 @@ __host__ __device__ inline Accel<T> chart_rhs(T a, const T x[4], const T k[4]) {
 // Scalar helpers for the norm, dispatched on type.
 __host__ __device__ inline double kabs(double x) { return fabs(x); }
 __host__ __device__ inline float kabs(float x) { return fabsf(x); }
-__host__ __device__ inline double kmax(double x, double y) { return x > y ? x : y; }
-__host__ __device__ inline float kmax(float x, float y) { return x > y ? x : y; }
+// The larger of two magnitudes (one v_max instruction; a NaN operand yields the
+// other operand, and a NaN error estimate rejects the attempt either way).
+__host__ __device__ inline double kmax(double x, double y) { return fmax(x, y); }
+__host__ __device__ inline float kmax(float x, float y) { return fmaxf(x, y); }
 
 struct DP5Tab {
   double c[7];
@@ -90,7 +94,11 @@ struct Conv {
 };
 
 // One Dormand-Prince attempt from (x, k) with acceleration a1 = acc(x, k).
-// State and stage arithmetic in TS; right-hand side evaluated in TR.
+// State, the new state's sums and the error estimate in TS; the stage values
+// and the stage inputs X_i, K_i in TA; the right-hand side in TR.  FP64 and
+// FP32 runs use one type throughout; the mixed-precision fast path runs
+// stages and right-hand side in FP32 (TA = TR = float) and keeps the state,
+// its update, the error estimate and the norm in FP64.
 // Outputs the 5th-order state (xn, kn), its acceleration a7 (first stage of
 // the next step) and the radius / radial rate at (xn, kn); returns the mean
 // square of the scaled error components, i.e. the square of the RMS error
@@ -101,57 +109,68 @@ struct Conv {
 // CTF: coordinate-time form (x = (t, x^i), k = (1, v^i), the right-hand side
 // rhs_ct; the t and v^0 slots have zero derivative and drop out of the norm,
 // which is then the RMS over the six evolved components).
-template <int FORM, typename TS, typename TR, bool CTF = false>
+template <int FORM, typename TS, typename TR, bool CTF = false, typename TA = TS>
 __host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], const TS a1[4], TS h, TS rtol,
                                           TS atol, TS xn[4], TS kn[4], TS a7[4], TS& r_new, TS& rdot_new) {
-  TS S[6][4];
+  TA S[6][4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) S[0][c] = a1[c];
+  for (int c = 0; c < 4; ++c) S[0][c] = Conv<TS, TA>::to(a1[c]);
   const TR ac = Conv<TS, TR>::to(a_c);
+  // h k and h^2 once per attempt: X_i = (x + c_i (h k)) + h^2 sum_l (A A)_il S_l
+  TA xa[4], ka[4], hkv[4];
+  const TA ha = Conv<TS, TA>::to(h);
+  hkv[0] = TA(0);  // t: unused
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    xa[c] = Conv<TS, TA>::to(x[c]);
+    ka[c] = Conv<TS, TA>::to(k[c]);
+    if (c > 0) hkv[c] = ha * ka[c];
+  }
+  const TA hh = ha * ha;
 #pragma unroll
   for (int i = 1; i < 6; ++i) {
     TR X[4], K[4];
     X[0] = TR(0);  // the metric is stationary: t never enters the right-hand side
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      TS sx = TS(0), sk = TS(0);
+      TA sx = TA(0), sk = TA(0);
       bool hx = false, hk = false;
 #pragma unroll
       for (int l = 0; l < i; ++l) {
         if (DP5.AA[i][l] != 0.0) {
-          sx = hx ? sx + TS(DP5.AA[i][l]) * S[l][c] : TS(DP5.AA[i][l]) * S[l][c];
+          sx = hx ? sx + TA(DP5.AA[i][l]) * S[l][c] : TA(DP5.AA[i][l]) * S[l][c];
           hx = true;
         }
         if (DP5.A[i][l] != 0.0) {
-          sk = hk ? sk + TS(DP5.A[i][l]) * S[l][c] : TS(DP5.A[i][l]) * S[l][c];
+          sk = hk ? sk + TA(DP5.A[i][l]) * S[l][c] : TA(DP5.A[i][l]) * S[l][c];
           hk = true;
         }
       }
-      if (c > 0) X[c] = Conv<TS, TR>::to(hx ? x[c] + h * (TS(DP5.c[i]) * k[c] + h * sx)
-                                            : x[c] + h * (TS(DP5.c[i]) * k[c]));
-      K[c] = Conv<TS, TR>::to(hk ? k[c] + h * sk : k[c]);
+      if (c > 0)
+        X[c] = Conv<TA, TR>::to(hx ? (xa[c] + TA(DP5.c[i]) * hkv[c]) + hh * sx : xa[c] + TA(DP5.c[i]) * hkv[c]);
+      K[c] = Conv<TA, TR>::to(hk ? ka[c] + ha * sk : ka[c]);
     }
     const Accel<TR> ra = CTF ? rhs_ct<FORM, TR>(ac, X, K) : rhs<FORM, TR>(ac, X, K);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) S[i][c] = Conv<TS, TR>::from(ra.a[c]);
+    for (int c = 0; c < 4; ++c) S[i][c] = Conv<TA, TR>::from(ra.a[c]);
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    TS sx = TS(0), sk = TS(0);
+    TA sx = TA(0), sk = TA(0);
     bool hx = false, hk = false;
 #pragma unroll
     for (int l = 0; l < 6; ++l) {
       if (DP5.bA[l] != 0.0) {
-        sx = hx ? sx + TS(DP5.bA[l]) * S[l][c] : TS(DP5.bA[l]) * S[l][c];
+        sx = hx ? sx + TA(DP5.bA[l]) * S[l][c] : TA(DP5.bA[l]) * S[l][c];
         hx = true;
       }
       if (DP5.b[l] != 0.0) {
-        sk = hk ? sk + TS(DP5.b[l]) * S[l][c] : TS(DP5.b[l]) * S[l][c];
+        sk = hk ? sk + TA(DP5.b[l]) * S[l][c] : TA(DP5.b[l]) * S[l][c];
         hk = true;
       }
     }
-    xn[c] = x[c] + h * (k[c] + h * sx);
-    kn[c] = k[c] + h * sk;
+    xn[c] = x[c] + h * (k[c] + h * Conv<TS, TA>::from(sx));
+    kn[c] = k[c] + h * Conv<TS, TA>::from(sk);
   }
   {
     TR X[4], K[4];
@@ -166,7 +185,8 @@ __host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], 
     r_new = Conv<TS, TR>::from(ra.r);
     rdot_new = Conv<TS, TR>::from(ra.rdot);
   }
-  TS s2 = TS(0);
+  const TS hhs = std::is_same<TA, TS>::value ? Conv<TS, TA>::from(hh) : h * h;
+  TS s2;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     TS ex = TS(0), ek = TS(0);
@@ -174,23 +194,25 @@ __host__ __device__ inline TS dp5_attempt(TS a_c, const TS x[4], const TS k[4], 
 #pragma unroll
     for (int l = 0; l < 6; ++l) {
       if (DP5.eA[l] != 0.0) {
-        ex = hx ? ex + TS(DP5.eA[l]) * S[l][c] : TS(DP5.eA[l]) * S[l][c];
+        const TS v = Conv<TS, TA>::from(S[l][c]);
+        ex = hx ? ex + TS(DP5.eA[l]) * v : TS(DP5.eA[l]) * v;
         hx = true;
       }
       if (DP5.e[l] != 0.0) {
-        ek = hk ? ek + TS(DP5.e[l]) * S[l][c] : TS(DP5.e[l]) * S[l][c];
+        const TS v = Conv<TS, TA>::from(S[l][c]);
+        ek = hk ? ek + TS(DP5.e[l]) * v : TS(DP5.e[l]) * v;
         hk = true;
       }
     }
     // the last-stage term goes last, so the stage values can die before the
     // final right-hand side is evaluated
     ek = ek + TS(DP5.e[6]) * a7[c];
-    ex = h * h * ex;
+    ex = hhs * ex;
     ek = h * ek;
     const TS sx = atol + rtol * kmax(kabs(x[c]), kabs(xn[c]));
     const TS sk = atol + rtol * kmax(kabs(k[c]), kabs(kn[c]));
     const TS qx = ex * krcp_est(sx), qk = ek * krcp_est(sk);
-    s2 = s2 + qx * qx + qk * qk;
+    s2 = c == 0 ? qx * qx + qk * qk : s2 + qx * qx + qk * qk;
   }
   return s2 * (CTF ? TS(1.0 / 6.0) : TS(0.125));
 }

@@ -141,3 +141,51 @@ def test_vertical_epicyclic_frequency_on_gpu(r):
     say(f"  r = {r}: Omega_z {got:.12f}, closed form {want:.12f}, rel {abs(got / want - 1):.2e}")
     assert got == pytest.approx(want, rel=1e-8)
     ctx.close()
+
+
+@pytest.mark.parametrize("r,bound", [(1.3, 2e-11), (1.4, 2e-11), (1.5, 2e-11)])
+def test_vertical_epicyclic_frequency_at_tight_tolerance(r, bound):
+    """The same orbit at the tolerance that brings the measurement closest to
+    the paper's Fig. OmegaV (better than 1e-13 for r < 1.5 there): DOPRI5 at
+    rtol 1e-14.  The frequency comes from half-periods between crossing 0 and
+    crossing c + 7 > 30: the crossing counter is reset by the caller after c
+    crossings (the state is caller-owned), so the next eight records are
+    crossings c .. c + 7.  Longer spans are worse, not better: the per-step
+    error moves the orbit's radius, and the frequency with it.  The oracle
+    measures 2e-12 - 5e-12 on this span; the bound leaves room for the GPU's
+    right-hand side (reciprocals refined to ~4e-15)."""
+    torch.cuda.set_device(0)
+    ctx = K.Context(0)
+    a = 1.0
+    om = cf.omega_kepler(r, a)
+    rho = np.sqrt(r * r + a * a)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    st = K.State(1, k_cross=8)
+    x3 = torch.tensor([[rho], [0.0], [0.0]], **f64)
+    v3 = torch.tensor([[0.0], [om * rho], [1e-12]], **f64)
+    ctx.kh_init_geodesics(K.TIMELIKE, torch.tensor([a], **f64), x3, v3, st)
+    p = K.kh_default_params(method=K.DOPRI5, rtol=1e-14, atol=1e-30, hmax_coeff=0.05, r_escape=1e4,
+                            r_h_factor=0.5, max_steps=4000, k_cross=8)
+
+    def run_until(count):
+        for _ in range(400):
+            ctx.kh_integrate(p, st)
+            torch.cuda.synchronize()
+            assert int(st.status[0].item()) == K.MAX_STEPS
+            if int(st.n_cross[0].item()) >= count:
+                return int(st.n_cross[0].item())
+        raise AssertionError("crossings not reached")
+
+    run_until(8)
+    first = st.cross[0, :, 1].cpu().numpy().copy()
+    c = run_until(24)
+    st.n_cross.zero_()
+    run_until(8)
+    second = st.cross[0, :, 1].cpu().numpy().copy()
+    halves = c + 7
+    got = np.pi * om * halves / (second[7] - first[0])
+    want = cf.omega_vertical(r, a)
+    rel = abs(got / want - 1)
+    say(f"  r = {r}, rtol 1e-14, {halves} half periods: Omega_z {got:.15f}, closed form {want:.15f}, rel {rel:.2e}")
+    assert rel < bound
+    ctx.close()

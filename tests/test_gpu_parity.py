@@ -359,13 +359,16 @@ def test_particles_to_t_end_parity(ctx):
     d = rel_pos(g["s"], o["s"])
     say(f"  max rel pos {d.max():.2e}, median {np.median(d):.2e}")
     assert d.max() < 1e-6
-    # Constant-of-motion drift grows about linearly with the number of orbits
-    # (up to ~100 here); it is reported, with a loose bound.
+    # Constant-of-motion drift grows with the number of accepted steps (each
+    # adds a local error of order rtol): per particle and per constant the
+    # oracle's drift on this sample stays below 1.92 n_acc rtol (Q; E 0.16,
+    # L_z 0.96, mu^2 0.44), and the GPU's must stay below twice that.
     drift = (np.abs(g["c1"] - g["c0"]) / np.maximum(np.abs(g["c0"]), 1.0))[:, landed]
+    per_step = drift / (g["n_acc"][landed] * p.rtol)
     say(f"  drift median/max E {np.median(drift[0]):.1e}/{drift[0].max():.1e} Lz {np.median(drift[1]):.1e}/"
         f"{drift[1].max():.1e} Q {np.median(drift[2]):.1e}/{drift[2].max():.1e} mu2 {np.median(drift[3]):.1e}/"
-        f"{drift[3].max():.1e}")
-    assert np.median(drift) < 1e-6 and drift.max() < 1e-3
+        f"{drift[3].max():.1e}; max drift / (n_acc rtol) {np.array2string(per_step.max(axis=1), precision=3)}")
+    assert np.all(per_step < 4.0)
 
 
 def test_particles_full_size_sampled(ctx):

@@ -63,7 +63,8 @@ def test_forward_matches_reference(ctx):
     got = y.cpu().numpy()
     want, _ = M.forward(p.astype(np.float64), x.astype(np.float64), bf16_storage=True)
     err = np.abs(got - want).max() / np.abs(want).max()
-    say(f"  max abs err / max |y| = {err:.2e}")
+    col = np.abs(got - want).max(axis=0) / np.abs(want).max(axis=0)
+    say(f"  max abs err / max |y| = {err:.2e}; per output {np.array2string(col, precision=2)}")
     assert err < 2e-2
     # and the plain FP64 network is close too (BF16 storage costs ~1e-2)
     plain, _ = M.forward(p.astype(np.float64), x.astype(np.float64))
@@ -97,6 +98,9 @@ def test_gradient_matches_reference(ctx):
     for nin, nout in M.LAYERS:
         for size in (nin * nout, nout):
             a, b = g[off:off + size], gw[off:off + size]
+            say(f"  block {nin}x{nout} size {size}: max |dg| / max |g| = "
+                f"{np.abs(a - b).max() / max(np.abs(b).max(), 1e-300):.2e}, "
+                f"max |dg| / (|g| + max|g|/10) = {np.max(np.abs(a - b) / (np.abs(b) + 0.1 * np.abs(b).max())):.2e}")
             if np.linalg.norm(b) > 0:
                 assert a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300) > 0.995, (nin, nout, size)
             off += size
