@@ -245,6 +245,22 @@ kh_status kh_init_geodesics(kh_ctx *ctx, int32_t kind, const double *spin, const
  * changes the run time only, never a result. */
 kh_status kh_integrate(kh_ctx *ctx, const kh_params *p, kh_state *st, void *stream);
 
+/* kh_integrate for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels, launch and results (bitwise), with no context.  It runs on the
+ * calling thread's current device and calls no hipMalloc, hipFree or other
+ * allocating routine.  Its only scratch is the work-queue counters, kept in a
+ * static device array of 16 64-bit counters (128 B) per GPU, held until the
+ * process ends; a call uses 8 of them whatever st->n is, so no state is too
+ * large for it, and queue_parts above 8 is refused with KH_EINVAL.  The first
+ * call on a device looks up that device's copy of the array
+ * (hipGetSymbolAddress); make it outside graph capture.  Every call on one
+ * GPU shares that array and each launch clears it first, so calls that
+ * overlap on one GPU (two streams, two threads) race: serialise them.
+ * Errors: the kh_integrate codes; the message (empty on success) is written
+ * to err, truncated to err_len bytes (err may be NULL). */
+kh_status kh_integrate_noalloc(const kh_params *p, kh_state *st, void *stream, char *err, int32_t err_len);
+
 /* Copy rays [first, first + count) to the host: host_s [count][8] (AoS, may be
  * NULL), host_status [count] (may be NULL).  The rows are packed on the device
  * in chunks of up to 2^20 rays, in context scratch of up to 64 MiB allocated

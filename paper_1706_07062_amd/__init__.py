@@ -74,8 +74,8 @@ MLP_WB_ELEMS = 208896
 MLP_WBT_ELEMS = 204800
 
 EXPORTS = ["kh_create", "kh_destroy", "kh_last_error", "kh_default_params", "kh_init_rays", "kh_init_rays_list",
-           "kh_init_geodesics", "kh_integrate", "kh_read_state", "kh_stats", "kh_stats_device", "kh_rhs", "kh_flops",
-           "kh_rk4_fixed", "kh_pack_fixed"]
+           "kh_init_geodesics", "kh_integrate", "kh_integrate_noalloc", "kh_read_state", "kh_stats", "kh_stats_device",
+           "kh_rhs", "kh_flops", "kh_rk4_fixed", "kh_pack_fixed"]
 MLP_EXPORTS = ["kh_mlp_work_bytes", "kh_mlp_sync", "kh_mlp_forward", "kh_mlp_image", "kh_mlp_targets", "kh_mlp_grad",
                "kh_mlp_train_step", "kh_init_rays_pixels", "kh_image_from_state"]
 
@@ -102,6 +102,7 @@ def lib():
         L.kh_init_rays_list.argtypes = [vp, vp, vp, vp, vp, d, P(kh_state), vp]
         L.kh_init_geodesics.argtypes = [vp, i32, vp, vp, vp, P(kh_state), vp]
         L.kh_integrate.argtypes = [vp, P(kh_params), P(kh_state), vp]
+        L.kh_integrate_noalloc.argtypes = [P(kh_params), P(kh_state), vp, C.c_char_p, i32]
         L.kh_read_state.argtypes = [vp, P(kh_state), i64, i64, vp, vp, vp]
         L.kh_stats.argtypes = [vp, P(kh_state), P(i64), vp]
         L.kh_stats_device.argtypes = [vp, P(kh_state), vp, vp]
@@ -147,6 +148,15 @@ def kh_default_params(**overrides) -> kh_params:
             raise AttributeError(k)
         setattr(p, k, v)
     return p
+
+
+def kh_integrate_noalloc(params: kh_params, st: "State", stream=None):
+    """kh_integrate without a context or any allocation (static work-queue
+    counters on the current device); raises KerrHipError on an error code."""
+    err = C.create_string_buffer(256)
+    rc = lib().kh_integrate_noalloc(C.byref(params), C.byref(st.c), _stream(stream), err, len(err))
+    if rc != KH_OK:
+        raise KerrHipError(f"kh_integrate_noalloc failed ({rc}): {err.value.decode()}")
 
 
 def kh_flops(method=DOPRI5, rhs_form=RHS_FACTORED) -> dict:

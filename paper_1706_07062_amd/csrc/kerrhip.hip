@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -1534,6 +1535,49 @@ kh_status launch_integrate(const kh_params* p, const kh_state* st, hipStream_t s
 
 #undef KH_TRY
 
+// Work-queue counters of kh_integrate_noalloc, for callers that cannot
+// allocate: one copy of this array per GPU the library runs on, held until the
+// process ends.  On the host the name `scratch` is only a stand-in for the
+// symbol, not a device address; host code uses the address that
+// hipGetSymbolAddress returns for the current device (noalloc_device below).
+constexpr int kNoAllocSlots = kQueueSlots;  // 16 x 8 B; an integrate call uses kParts of them
+static_assert(kParts <= kNoAllocSlots, "the static array holds every queue partition's counter");
+static __device__ __align__(256) unsigned long long scratch[kNoAllocSlots];
+
+constexpr int kMaxDevices = 64;
+struct NoAllocDevice {
+  unsigned long long* q = nullptr;  // device address of `scratch` on this device
+  int n_cu = 0;
+};
+NoAllocDevice g_noalloc[kMaxDevices];
+std::mutex g_noalloc_mu;
+
+// Set-up of the current device, once per device: the address of its copy of
+// `scratch` and its compute-unit count.  Allocates nothing.
+const char* noalloc_device(NoAllocDevice* out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return "hipGetDevice failed";
+  if (dev < 0 || dev >= kMaxDevices) return "device index beyond the library's table of 64 devices";
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  NoAllocDevice& d = g_noalloc[dev];
+  if (!d.q) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_msg(e, "hipGetSymbolAddress(scratch)");
+    int n_cu = 0;
+    e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_msg(e, "hipDeviceGetAttribute(multiprocessor count)");
+    d.n_cu = n_cu;
+    d.q = static_cast<unsigned long long*>(ptr);
+  }
+  *out = d;
+  return nullptr;
+}
+
+void copy_msg(char* err, int32_t err_len, const char* m) {
+  if (err && err_len > 0) std::snprintf(err, (size_t)err_len, "%s", m ? m : "");
+}
+
 }  // namespace
 
 extern "C" {
@@ -1548,6 +1592,25 @@ kh_status kh_integrate(kh_ctx* ctx, const kh_params* p, kh_state* st, void* stre
   const char* msg = nullptr;
   s = launch_integrate(p, st, (hipStream_t)stream, ctx->d_queue, ctx->n_cu, &msg);
   return s == KH_OK ? KH_OK : fail(ctx, s, msg ? msg : "kh_integrate");
+}
+
+kh_status kh_integrate_noalloc(const kh_params* p, kh_state* st, void* stream, char* err, int32_t err_len) {
+  copy_msg(err, err_len, "");
+  g_skip_ptr_query = capturing(stream);
+  kh_status code;
+  if (const char* m = params_problem(p, st, &code)) {
+    copy_msg(err, err_len, m);
+    return code;
+  }
+  NoAllocDevice d;
+  if (const char* m = noalloc_device(&d)) {
+    copy_msg(err, err_len, m);
+    return KH_EHIP;
+  }
+  const char* msg = nullptr;
+  const kh_status s = launch_integrate(p, st, (hipStream_t)stream, d.q, d.n_cu, &msg);
+  if (s != KH_OK) copy_msg(err, err_len, msg ? msg : "kh_integrate_noalloc");
+  return s;
 }
 
 kh_status kh_read_state(kh_ctx* ctx, const kh_state* st, int64_t first, int64_t count, double* host_s,
