@@ -51,9 +51,9 @@ def kernel_source_hash():
 # (FETCH_SIZE, WRITE_SIZE, calibrated against a plain copy) and hardware FP64
 # FLOP per launch (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes), valid only for the
 # kernel source they were taken on.
-PROFILED = {"source_hash": "91397afda309dd9a",
-            "traffic_bytes": (120918.09375 * 2.0 + 316734.8125 * 1.0) * 1024,
-            "hw_fp64_flops": 6195199816.5 * 64}
+PROFILED = {"source_hash": "5390b35928620156",
+            "traffic_bytes": (120631.0 * 2.0 + 318170.5 * 1.0) * 1024,
+            "hw_fp64_flops": 5803115000.0 * 64}
 
 
 def algorithmic_flops(K, stats, n_rays, method, form):
