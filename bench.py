@@ -341,8 +341,8 @@ def elapse_extra(ctx, K, W, torch, reps=5):
 def surrogate_extra(ctx, K, W, torch, args):
     """Learned surrogate: integrate 1e7 random rays (FP64 DOPRI5), train the
     BF16-MFMA network on them, then render the 4096x4096 a = 0.9, 45 deg image
-    with integrator fallback on uncertain pixels, against the integrator's own
-    image of the same camera."""
+    with integrator fallback under several fallback settings, against the
+    integrator's own image of the same camera."""
     from paper_1706_07062_amd import surrogate as S
 
     sur = S.Surrogate(ctx, seed=0, max_batch=8192)
@@ -350,27 +350,32 @@ def surrogate_extra(ctx, K, W, torch, args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist = sur.train(x, t, mask, steps=args.surrogate_steps, batch=8192, lr=2e-3,
-                     log_every=max(1, args.surrogate_steps // 8), log=log)
+                     log_every=max(1, args.surrogate_steps // 8), log=log, loss_w=S.LOSS_WEIGHTS)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     cam = W.surrogate_eval_camera()
     S.integrate_image(ctx, cam)  # warm-up
     ref, t_int = S.integrate_image(ctx, cam)
     curve = []
-    for tau in (0.45, 0.2, 0.05, 0.01, 0.001):
-        sur.render(cam, tau)  # warm-up
-        img, tm = sur.render(cam, tau)
+    # (tau, shadow_band [M], r_min [M]): capture band alone, then with the
+    # shadow-edge and strong-field rules
+    for tau, band, r_min in ((0.45, 0.0, 0.0), (0.2, 0.0, 0.0), (0.05, 0.0, 0.0), (0.01, 0.0, 0.0),
+                             (0.2, 0.1, 0.0), (0.2, 0.3, 0.0), (0.2, 0.3, 3.0), (0.05, 0.3, 4.0)):
+        sur.render(cam, tau, shadow_band=band, r_min=r_min)  # warm-up
+        img, tm = sur.render(cam, tau, shadow_band=band, r_min=r_min)
         err = S.image_error(img, ref)
-        curve.append(dict(tau=tau, speedup=t_int / tm["total_s"], **tm, **err))
-        log(f"surrogate tau {tau}: speedup {t_int / tm['total_s']:.2f}, fallback {tm['fallback_fraction']:.4f}, "
-            f"capture mismatch {err['capture_mismatch']:.2e}, |dg| p99 {err['g_abs_p99']:.2e}")
+        curve.append(dict(tau=tau, shadow_band=band, r_min=r_min, speedup=t_int / tm["total_s"], **tm, **err))
+        log(f"surrogate tau {tau} band {band} r_min {r_min}: speedup {t_int / tm['total_s']:.2f}, fallback "
+            f"{tm['fallback_fraction']:.4f}, capture mismatch {err['capture_mismatch']:.2e}, "
+            f"|dg| p99 {err['g_abs_p99']:.2e}")
     # fixed-error point: the fastest setting with no more than 1e-4 capture
     # mismatches and p99 |dg| <= 1e-3; None when no setting meets both
     ok = [c for c in curve if c["capture_mismatch"] <= 1e-4 and c["g_abs_p99"] <= 1e-3]
     best = max(ok, key=lambda c: c["speedup"]) if ok else None
     return dict(train_rays=args.surrogate_rays, data_s=t_data, train_steps=args.surrogate_steps, batch=8192,
-                train_s=t_train, loss_history=hist, integrator_s=t_int, image=f"{cam.width}x{cam.height}",
-                curve=curve, at_fixed_error=best, fixed_error_met=best is not None,
+                loss_weights=dict(zip(("r", "phi", "g", "capture"), S.LOSS_WEIGHTS)), train_s=t_train,
+                loss_history=hist, integrator_s=t_int, image=f"{cam.width}x{cam.height}", curve=curve,
+                at_fixed_error=best, fixed_error_met=best is not None,
                 fixed_error="capture-flag mismatch <= 1e-4 of pixels and p99 |dg| <= 1e-3 on pixels where both "
                             "images have a crossing; r and phi errors stated alongside")
 
@@ -620,7 +625,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, help="MiB; plain copy before the run (counter reference)")
     ap.add_argument("--surrogate-rays", type=int, default=10_000_000)
-    ap.add_argument("--surrogate-steps", type=int, default=8000)
+    ap.add_argument("--surrogate-steps", type=int, default=40000)
     ap.add_argument("--precision-only", action="store_true",
                     help="only the FP32, MIXED and coordinate-time launches on the benchmark images (for profilers)")
     ap.add_argument("--elapse-only", action="store_true",

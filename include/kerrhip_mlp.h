@@ -50,6 +50,10 @@ typedef struct {
   int32_t step;                /* 1-based step count for bias correction */
 } kh_adam;
 
+typedef struct {
+  float r, phi, g, capture; /* weights of the four loss terms (see kh_mlp_grad); all >= 0 */
+} kh_mlp_loss_w;
+
 /* Bytes of the training workspace for batches of up to max_batch rays
  * (max_batch a multiple of 256). */
 int64_t kh_mlp_work_bytes(int32_t max_batch);
@@ -62,12 +66,24 @@ kh_status kh_mlp_sync(kh_ctx *ctx, const kh_mlp *net, void *stream);
  * features x [m][4] = (alpha, beta, a, incl_radians), FP32 device arrays. */
 kh_status kh_mlp_forward(kh_ctx *ctx, const kh_mlp *net, const float *x, float *y, int64_t m, void *stream);
 
+/* Which pixels of a surrogate image go back to the integrator (any rule that
+ * holds sends the pixel). */
+typedef struct {
+  float tau;         /* capture uncertain: tau < p_capture < 1 - tau; tau in [0, 0.5) */
+  float shadow_band; /* near the shadow edge: within this distance (M, image plane) of the
+                        critical curve of the camera's spin and inclination (Bardeen's closed
+                        form for a distant observer); 0 = off (also for sin(incl) < 1e-3) */
+  float r_min;       /* strong field: predicted first crossing inside r_min (M) and
+                        p_capture <= 1/2, where the crossing radius and the redshift change
+                        fastest across the image; 0 = off */
+} kh_mlp_fallback;
+
 /* The surrogate image of one camera: out [w*h][4] = (r, phi, g, p_capture)
- * decoded from the network, pixel order as kh_init_rays.  Pixels with
- * tau < p_capture < 1 - tau are appended (in any order) to fallback_ids
- * (device int32, capacity w*h) and counted in *fallback_count (device int32,
- * zeroed by the call). */
-kh_status kh_mlp_image(kh_ctx *ctx, const kh_mlp *net, const kh_camera *cam, float tau, float *out,
+ * decoded from the network, pixel order as kh_init_rays.  Pixels that a rule
+ * of *fb selects are appended (in any order) to fallback_ids (device int32,
+ * capacity w*h) and counted in *fallback_count (device int32, zeroed by the
+ * call).  fb is a host struct (required). */
+kh_status kh_mlp_image(kh_ctx *ctx, const kh_mlp *net, const kh_camera *cam, const kh_mlp_fallback *fb, float *out,
                        int32_t *fallback_ids, int32_t *fallback_count, void *stream);
 
 /* Training data from integrated rays: st (with one crossing slot or more) and
@@ -80,16 +96,18 @@ kh_status kh_mlp_targets(kh_ctx *ctx, const kh_state *st, const double *alpha, c
 /* Gradient of the mean loss over a batch of b rays (b a multiple of 256, at
  * most the workspace's max_batch) into grad [KH_MLP_NPARAMS] (FP32 device),
  * and the batch loss into *loss (device float; accumulated, caller zeroes).
- * Loss per ray: mask0 ((y0 - t0)^2 + (y1 - t1)^2) + mask1 (y2 - t2)^2 +
- * BCE(sigmoid(y3), t3). */
+ * Loss per ray: mask0 (w.r (y0 - t0)^2 + w.phi (y1 - t1)^2) + mask1 w.g
+ * (y2 - t2)^2 + w.capture BCE(sigmoid(y3), t3), with the weights of *lw (a
+ * host struct; NULL = all 1; KH_EINVAL unless each is in [0, 1e6)). */
 kh_status kh_mlp_grad(kh_ctx *ctx, const kh_mlp *net, void *work, int32_t max_batch, const float *x, const float *t,
-                      const uint8_t *mask, int32_t b, float *grad, float *loss, void *stream);
+                      const uint8_t *mask, int32_t b, const kh_mlp_loss_w *lw, float *grad, float *loss,
+                      void *stream);
 
 /* One Adam step on a batch: gradient as kh_mlp_grad, then the update of params,
  * moments and BF16 copies. */
 kh_status kh_mlp_train_step(kh_ctx *ctx, const kh_mlp *net, void *work, int32_t max_batch, const float *x,
-                            const float *t, const uint8_t *mask, int32_t b, const kh_adam *opt, float *loss,
-                            void *stream);
+                            const float *t, const uint8_t *mask, int32_t b, const kh_mlp_loss_w *lw,
+                            const kh_adam *opt, float *loss, void *stream);
 
 /* Rays of the listed pixels of one camera: st->n = number of ids in pix
  * (device int32 [st->n]), same outputs as kh_init_rays; st->order and

@@ -46,13 +46,16 @@ def sigmoid(z):
 
 
 def forward(params, x, bf16_storage=False):
-    """Network outputs.  bf16_storage=True rounds the weights, the inputs and
-    every hidden activation to BF16 (the storage format of the GPU's matrix
-    products), keeping FP64 arithmetic otherwise."""
+    """Network outputs.  bf16_storage=True rounds the weights and every hidden
+    activation to BF16 and the inputs to a sum of two BF16 numbers (the storage
+    format of the GPU's matrix products), keeping FP64 arithmetic otherwise."""
     h = features(x)
     layers = unpack(params)
     if bf16_storage:
-        h = round_bf16(h)
+        # the inputs enter as two BF16 terms each (leading term and the
+        # rounded remainder), the other activations as one
+        hi = round_bf16(h)
+        h = hi + round_bf16(h - hi)
         layers = [(round_bf16(W), b) for W, b in layers]
     cache = [h]
     zs = []
@@ -69,9 +72,9 @@ def forward(params, x, bf16_storage=False):
     return h, (cache, zs)
 
 
-def loss_and_grad(params, x, t, mask, bf16_storage=False):
-    """Mean over the batch of mask0 ((y0-t0)^2 + (y1-t1)^2) + mask1 (y2-t2)^2 +
-    BCE(sigmoid(y3), t3), and its gradient (flat, like params).  With
+def loss_and_grad(params, x, t, mask, bf16_storage=False, weights=(1.0, 1.0, 1.0, 1.0)):
+    """Mean over the batch of mask0 (w0 (y0-t0)^2 + w1 (y1-t1)^2) + mask1 w2 (y2-t2)^2 +
+    w3 BCE(sigmoid(y3), t3), and its gradient (flat, like params).  With
     bf16_storage the forward pass stores weights and activations as BF16."""
     y, (hs, zs) = forward(params, x, bf16_storage)
     if bf16_storage:
@@ -82,8 +85,9 @@ def loss_and_grad(params, x, t, mask, bf16_storage=False):
     e0, e1, e2 = (y[:, 0] - t[:, 0]) * m0, (y[:, 1] - t[:, 1]) * m0, (y[:, 2] - t[:, 2]) * m1
     y3, t3 = y[:, 3], t[:, 3]
     bce = np.maximum(y3, 0) - y3 * t3 + np.log1p(np.exp(-np.abs(y3)))
-    loss = np.mean(e0 ** 2 + e1 ** 2 + e2 ** 2 + bce)
-    dy = np.stack([2 * e0, 2 * e1, 2 * e2, sigmoid(y3) - t3], axis=1) / n
+    w0, w1, w2, w3 = (float(v) for v in weights)
+    loss = np.mean(w0 * e0 ** 2 + w1 * e1 ** 2 + w2 * e2 ** 2 + w3 * bce)
+    dy = np.stack([2 * w0 * e0, 2 * w1 * e1, 2 * w2 * e2, w3 * (sigmoid(y3) - t3)], axis=1) / n
     layers = unpack(params)
     grads = [None] * len(layers)
     d = dy

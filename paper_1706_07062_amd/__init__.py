@@ -64,6 +64,14 @@ class kh_mlp(C.Structure):
                 ("wbt", C.c_void_p)]
 
 
+class kh_mlp_loss_w(C.Structure):
+    _fields_ = [("r", C.c_float), ("phi", C.c_float), ("g", C.c_float), ("capture", C.c_float)]
+
+
+class kh_mlp_fallback(C.Structure):
+    _fields_ = [("tau", C.c_float), ("shadow_band", C.c_float), ("r_min", C.c_float)]
+
+
 class kh_adam(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
                 ("step", C.c_int32)]
@@ -114,10 +122,11 @@ def lib():
         L.kh_mlp_work_bytes.restype = i64
         L.kh_mlp_sync.argtypes = [vp, P(kh_mlp), vp]
         L.kh_mlp_forward.argtypes = [vp, P(kh_mlp), vp, vp, i64, vp]
-        L.kh_mlp_image.argtypes = [vp, P(kh_mlp), P(kh_camera), C.c_float, vp, vp, vp, vp]
+        L.kh_mlp_image.argtypes = [vp, P(kh_mlp), P(kh_camera), P(kh_mlp_fallback), vp, vp, vp, vp]
         L.kh_mlp_targets.argtypes = [vp, P(kh_state), vp, vp, vp, vp, vp, vp, vp, vp]
-        L.kh_mlp_grad.argtypes = [vp, P(kh_mlp), vp, i32, vp, vp, vp, i32, vp, vp, vp]
-        L.kh_mlp_train_step.argtypes = [vp, P(kh_mlp), vp, i32, vp, vp, vp, i32, P(kh_adam), vp, vp]
+        L.kh_mlp_grad.argtypes = [vp, P(kh_mlp), vp, i32, vp, vp, vp, i32, P(kh_mlp_loss_w), vp, vp, vp]
+        L.kh_mlp_train_step.argtypes = [vp, P(kh_mlp), vp, i32, vp, vp, vp, i32, P(kh_mlp_loss_w), P(kh_adam), vp,
+                                        vp]
         L.kh_init_rays_pixels.argtypes = [vp, P(kh_camera), vp, P(kh_state), vp]
         L.kh_image_from_state.argtypes = [vp, P(kh_state), vp, vp, vp]
         for name in EXPORTS + MLP_EXPORTS:
@@ -356,12 +365,16 @@ def _mlp_methods():
         self._check(lib().kh_mlp_forward(self.handle, C.byref(net.c), x.data_ptr(), y.data_ptr(), m,
                                          _stream(stream)), "kh_mlp_forward")
 
-    def kh_mlp_image(self, net: Mlp, cam: kh_camera, tau, out, fb_ids, fb_count, stream=None):
+    def kh_mlp_image(self, net: Mlp, cam: kh_camera, tau, out, fb_ids, fb_count, stream=None, shadow_band=0.0,
+                     r_min=0.0):
+        """Fallback rules: capture band tau, shadow-edge band (M) and strong-field
+        radius r_min (M), as kh_mlp_fallback."""
         npix = cam.width * cam.height
         _dev(out, torch.float32, 4 * npix)
         _dev(fb_ids, torch.int32, npix, align=4)
         _dev(fb_count, torch.int32, 1, align=4)
-        self._check(lib().kh_mlp_image(self.handle, C.byref(net.c), C.byref(cam), float(tau), out.data_ptr(),
+        fb = kh_mlp_fallback(float(tau), float(shadow_band), float(r_min))
+        self._check(lib().kh_mlp_image(self.handle, C.byref(net.c), C.byref(cam), C.byref(fb), out.data_ptr(),
                                        fb_ids.data_ptr(), fb_count.data_ptr(), _stream(stream)), "kh_mlp_image")
 
     def kh_mlp_targets(self, st: "State", alpha, beta, spin, incl, x, t, mask, stream=None):
@@ -374,15 +387,19 @@ def _mlp_methods():
                                          spin.data_ptr(), incl.data_ptr(), x.data_ptr(), t.data_ptr(),
                                          mask.data_ptr(), _stream(stream)), "kh_mlp_targets")
 
-    def kh_mlp_grad(self, net: Mlp, work, max_batch, x, t, mask, b, grad, loss, stream=None):
+    def kh_mlp_grad(self, net: Mlp, work, max_batch, x, t, mask, b, grad, loss, stream=None, loss_w=None):
+        """loss_w: (r, phi, g, capture) weights of the loss terms, or None for all 1."""
         _dev(grad, torch.float32, MLP_NPARAMS)
+        lw = C.byref(kh_mlp_loss_w(*loss_w)) if loss_w is not None else None
         self._check(lib().kh_mlp_grad(self.handle, C.byref(net.c), work.data_ptr(), max_batch, x.data_ptr(),
-                                      t.data_ptr(), mask.data_ptr(), b, grad.data_ptr(), loss.data_ptr(),
+                                      t.data_ptr(), mask.data_ptr(), b, lw, grad.data_ptr(), loss.data_ptr(),
                                       _stream(stream)), "kh_mlp_grad")
 
-    def kh_mlp_train_step(self, net: Mlp, work, max_batch, x, t, mask, b, opt: kh_adam, loss, stream=None):
+    def kh_mlp_train_step(self, net: Mlp, work, max_batch, x, t, mask, b, opt: kh_adam, loss, stream=None,
+                          loss_w=None):
+        lw = C.byref(kh_mlp_loss_w(*loss_w)) if loss_w is not None else None
         self._check(lib().kh_mlp_train_step(self.handle, C.byref(net.c), work.data_ptr(), max_batch, x.data_ptr(),
-                                            t.data_ptr(), mask.data_ptr(), b, C.byref(opt), loss.data_ptr(),
+                                            t.data_ptr(), mask.data_ptr(), b, lw, C.byref(opt), loss.data_ptr(),
                                             _stream(stream)), "kh_mlp_train_step")
 
     def kh_init_rays_pixels(self, cam: kh_camera, pix, st: "State", stream=None):

@@ -19,6 +19,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <utility>
+#include <vector>
 
 #include "internal.hpp"
 #include "kerrhip_mlp.h"
@@ -75,6 +77,24 @@ __device__ inline float dsilu(float z) {
   return s * (1.0f + z * (1.0f - s));
 }
 
+// Layer-0 B operand of one ray: the four features in two BF16 terms each,
+// hi = bf16(f) in k = 0..3 and lo = bf16(f - hi) in k = 4..7 (the forward
+// weight copy repeats W0 in columns 4..7), so the product sees the features
+// to ~2^-16 instead of 2^-8: at BF16 alone an image coordinate would be
+// quantised to 12 x 2^-8 = 0.047 M over |alpha| in [6, 12], several pixels of
+// a 4096^2 image.  Lanes of the upper half hold k = 8..15 (zero).
+__device__ inline bf16x8 input_operand(const float f[4], int half) {
+  bf16x8 bx;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const __bf16 hi = (__bf16)f[j];
+    const __bf16 lo = (__bf16)(f[j] - (float)hi);
+    bx[j] = half == 0 ? hi : (__bf16)0.0f;
+    bx[4 + j] = half == 0 ? lo : (__bf16)0.0f;
+  }
+  return bx;
+}
+
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -84,6 +104,8 @@ __device__ inline f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c)
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
+constexpr int kCritBins = 128;  // angle bins of the critical-curve table
+
 struct FwdArgs {
   const float* params;
   const __bf16* wb;
@@ -91,7 +113,11 @@ struct FwdArgs {
   int64_t m;
   kh_camera cam;   // mode 1
   float* y;        // raw outputs [m][4], or the decoded image (camera mode)
-  float tau;
+  float tau;       // camera mode fallback rules (kh_mlp_fallback)
+  float crit_band;
+  float r_min;
+  float crit_ac;                // centre (crit_ac, 0) of the critical-curve table
+  float crit_r[kCritBins];      // its radius in equal angle bins over (-pi, pi]
   int32_t* fb_ids;
   int32_t* fb_count;
   float* z;    // training: pre-activations [4][bmax][256]
@@ -149,9 +175,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         norm_features(xv[0], xv[1], xv[2], xv[3], f);
       }
     }
-    bf16x8 bx;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) bx[j] = (half == 0 && j < 4) ? (__bf16)f[j] : (__bf16)0.0f;
+    const bf16x8 bx = input_operand(f, half);
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt) {
       const bf16x8 aw =
@@ -228,7 +252,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       d[2] = 0.3f * y[2] + 0.8f;
       d[3] = pc;
       *reinterpret_cast<f32x4*>(A.y + ray * 4) = d;
+      // the integrator takes the pixel when the capture is uncertain, when it
+      // lies near the critical curve (shadow edge), or when its predicted first
+      // crossing is deep in the potential well, where r and g change fastest
       unsure = pc > A.tau && pc < 1.0f - A.tau;
+      unsure = unsure || (pc <= 0.5f && d[0] < A.r_min);
+      if (A.crit_band > 0.0f) {
+        const int64_t row = ray / A.cam.width, col = ray % A.cam.width;
+        const float da = (float)(A.cam.alpha_min + (col + 0.5) * (A.cam.alpha_max - A.cam.alpha_min) / A.cam.width) -
+                         A.crit_ac;
+        const float be = (float)(A.cam.beta_min + (row + 0.5) * (A.cam.beta_max - A.cam.beta_min) / A.cam.height);
+        const float u = (atan2f(be, da) + 3.14159265358979f) * (kCritBins / (2.0f * 3.14159265358979f)) - 0.5f;
+        const float fl = floorf(u);
+        const float fr = u - fl;
+        const int k0 = ((int)fl + kCritBins) % kCritBins, k1 = (k0 + 1) % kCritBins;
+        const float rc = A.crit_r[k0] + fr * (A.crit_r[k1] - A.crit_r[k0]);
+        unsure = unsure || fabsf(sqrtf(da * da + be * be) - rc) < A.crit_band;
+      }
     } else {
       *reinterpret_cast<f32x4*>(A.y + ray * 4) = y;
     }
@@ -266,9 +306,8 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_train(FwdArgs A) {
     const f32x4 xv = *reinterpret_cast<const f32x4*>(A.x + ray * 4);
     norm_features(xv[0], xv[1], xv[2], xv[3], f);
   }
-  bf16x8 bx;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) bx[j] = (half == 0 && j < 4) ? (__bf16)f[j] : (__bf16)0.0f;
+  const bf16x8 bx = input_operand(f, half);
+  // the weight gradient of layer 0 uses the leading BF16 term of each feature
   if (w == 0 && valid) {
     __bf16* ht0 = ht_layer(A.ht, 0, A.bmax);
 #pragma unroll
@@ -348,8 +387,8 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_train(FwdArgs A) {
 
 // Loss and its gradient with respect to the raw outputs; dz [bmax][32] and
 // dzT [32][bmax] (BF16, columns / rows 4..31 zero).
-__global__ void k_mlp_loss(const float* y, const float* t, const uint8_t* mask, int64_t b, __bf16* dz, __bf16* dzT,
-                           int64_t bmax, float* loss) {
+__global__ void k_mlp_loss(const float* y, const float* t, const uint8_t* mask, int64_t b, kh_mlp_loss_w wl,
+                           __bf16* dz, __bf16* dzT, int64_t bmax, float* loss) {
   __shared__ float part[4];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   float l = 0.0f;
@@ -363,8 +402,9 @@ __global__ void k_mlp_loss(const float* y, const float* t, const uint8_t* mask, 
     const float e2 = (mk & 2) ? yv[2] - tv[2] : 0.0f;
     const float s = sigmoidf(yv[3]);
     const float bce = fmaxf(yv[3], 0.0f) - yv[3] * tv[3] + log1pf(__expf(-fabsf(yv[3])));
-    l = e0 * e0 + e1 * e1 + e2 * e2 + bce;
-    const float d[4] = {2.0f * e0 * inv, 2.0f * e1 * inv, 2.0f * e2 * inv, (s - tv[3]) * inv};
+    l = wl.r * (e0 * e0) + wl.phi * (e1 * e1) + wl.g * (e2 * e2) + wl.capture * bce;
+    const float d[4] = {2.0f * wl.r * e0 * inv, 2.0f * wl.phi * e1 * inv, 2.0f * wl.g * e2 * inv,
+                        wl.capture * (s - tv[3]) * inv};
 #pragma unroll
     for (int c = 0; c < 32; ++c) {
       const __bf16 v = (__bf16)(c < 4 ? d[c] : 0.0f);
@@ -493,6 +533,7 @@ __device__ inline void write_bf16(int p, float w, __bf16* wb, __bf16* wbt) {
   const int kpad = l == 0 ? 16 : 256;
   const int offwb = l == 0 ? 0 : l == 1 ? 4096 : l == 2 ? 69632 : l == 3 ? 135168 : 200704;
   wb[offwb + o * kpad + i] = (__bf16)w;
+  if (l == 0) wb[offwb + o * kpad + 4 + i] = (__bf16)w;  // the lo terms of the split inputs
   if (wbt && l >= 1) {
     const int mpad = l == 4 ? 32 : 256;
     const int offwbt = (l - 1) * 65536;
@@ -628,7 +669,8 @@ kh_status check_net(kh_ctx* ctx, const kh_mlp* net, bool train) {
 
 // Shared body of kh_mlp_grad and kh_mlp_train_step.
 kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batch, const float* x, const float* t,
-                    const uint8_t* mask, int32_t b, float* loss, hipStream_t strm, Work* out_w) {
+                    const uint8_t* mask, int32_t b, const kh_mlp_loss_w* lw, float* loss, hipStream_t strm,
+                    Work* out_w) {
   if (max_batch < 256 || max_batch % 256) return fail(ctx, KH_EINVAL, "max_batch must be a positive multiple of 256");
   if (b < 256 || b % 256 || b > max_batch) return fail(ctx, KH_EINVAL, "b must be a multiple of 256 <= max_batch");
   const void* ins[] = {x, t, mask, loss, work};
@@ -636,6 +678,13 @@ kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batc
     if (!q || !device_ok(q)) return fail(ctx, KH_EINVAL, "x, t, mask, loss and work must be device memory");
   if (!aligned(x, 16) || !aligned(t, 16) || !aligned(work, 256))
     return fail(ctx, KH_EINVAL, "x, t must be 16-byte aligned and work 256-byte aligned");
+  kh_mlp_loss_w wl = {1.0f, 1.0f, 1.0f, 1.0f};
+  if (lw) {
+    wl = *lw;
+    const float ws[4] = {wl.r, wl.phi, wl.g, wl.capture};
+    for (float v : ws)
+      if (!(v >= 0.0f) || !(v < 1e6f)) return fail(ctx, KH_EINVAL, "loss weights must be in [0, 1e6)");
+  }
   const int64_t bmax = max_batch;
   Work w = carve(work, bmax, nullptr);
   *out_w = w;
@@ -649,8 +698,8 @@ kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batc
   A.ht = w.ht;
   A.bmax = bmax;
   hipLaunchKernelGGL(k_mlp_fwd_train, dim3((unsigned)(b / RAYS)), dim3(256), 0, strm, A);
-  hipLaunchKernelGGL(k_mlp_loss, dim3((unsigned)(b / 256)), dim3(256), 0, strm, w.y, t, mask, (int64_t)b, w.dz4,
-                     w.dz4T, bmax, loss);
+  hipLaunchKernelGGL(k_mlp_loss, dim3((unsigned)(b / 256)), dim3(256), 0, strm, w.y, t, mask, (int64_t)b, wl,
+                     w.dz4, w.dz4T, bmax, loss);
   const __bf16* wbt = reinterpret_cast<const __bf16*>(net->wbt);
   auto ht = [&](int l) { return ht_layer(w.ht, l, bmax); };
   auto zl = [&](int l) { return w.z + (int64_t)l * bmax * HID; };
@@ -731,7 +780,75 @@ kh_status kh_mlp_forward(kh_ctx* ctx, const kh_mlp* net, const float* x, float* 
   return KH_OK;
 }
 
-kh_status kh_mlp_image(kh_ctx* ctx, const kh_mlp* net, const kh_camera* cam, float tau, float* out,
+}  // extern "C"
+
+namespace {
+// The critical curve of a camera (the shadow boundary seen from infinity,
+// Bardeen's closed form): photons on spherical orbits of radius r between the
+// prograde and retrograde circular photon orbits have xi = L_z / E and
+// eta = Q / E^2 from R(r) = R'(r) = 0,
+//   xi = (r^2 (3 - r) - a^2 (r + 1)) / (a (r - 1)),
+//   eta = r^3 (4 a^2 - r (r - 3)^2) / (a^2 (r - 1)^2),
+// and reach the image at alpha = -xi / sin i, beta = +-sqrt(eta + a^2 cos^2 i
+// - xi^2 cot^2 i).  The curve is tabulated as its radius around (ac, 0) in
+// kCritBins equal angle bins (it is star-shaped about that centre); a = 0
+// gives the circle of radius sqrt(27).  Returns false for a face-on camera
+// (sin i < 1e-3), where the formula degenerates; the rule is then off.
+bool critical_curve(double a, double incl, float* ac, float* rad) {
+  const double si = std::sin(incl), ci = std::cos(incl);
+  if (std::fabs(si) < 1e-3) return false;
+  if (std::fabs(a) < 1e-9) {
+    *ac = 0.0f;
+    for (int k = 0; k < kCritBins; ++k) rad[k] = (float)std::sqrt(27.0);
+    return true;
+  }
+  const double aa = std::fabs(a);
+  const double r1 = 2.0 * (1.0 + std::cos(2.0 / 3.0 * std::acos(-aa)));
+  const double r2 = 2.0 * (1.0 + std::cos(2.0 / 3.0 * std::acos(aa)));
+  constexpr int n = 4096;
+  std::vector<std::pair<double, double>> pts;  // (alpha, beta)
+  pts.reserve(2 * n);
+  for (int j = 0; j <= n; ++j) {
+    const double r = r1 + (r2 - r1) * j / n;
+    const double xi = (r * r * (3.0 - r) - a * a * (r + 1.0)) / (a * (r - 1.0));
+    const double eta = r * r * r * (4.0 * a * a - r * (r - 3.0) * (r - 3.0)) / (a * a * (r - 1.0) * (r - 1.0));
+    const double b2 = eta + a * a * ci * ci - xi * xi * ci * ci / (si * si);
+    if (!(b2 >= 0.0)) continue;
+    pts.emplace_back(-xi / si, std::sqrt(b2));
+    pts.emplace_back(-xi / si, -std::sqrt(b2));
+  }
+  if (pts.size() < 16) return false;
+  double amin = pts[0].first, amax = pts[0].first;
+  for (const auto& q : pts) {
+    amin = std::min(amin, q.first);
+    amax = std::max(amax, q.first);
+  }
+  const double c = 0.5 * (amin + amax);
+  std::vector<std::pair<double, double>> pol;  // (angle, radius) about (c, 0)
+  pol.reserve(pts.size());
+  for (const auto& q : pts) pol.emplace_back(std::atan2(q.second, q.first - c), std::hypot(q.first - c, q.second));
+  std::sort(pol.begin(), pol.end());
+  const int np = (int)pol.size();
+  for (int k = 0; k < kCritBins; ++k) {
+    const double th = -M_PI + (k + 0.5) * (2.0 * M_PI / kCritBins);
+    // first tabulated angle at or after th, and its predecessor (periodic)
+    int hi = (int)(std::lower_bound(pol.begin(), pol.end(), std::make_pair(th, -1.0)) - pol.begin());
+    const int lo = (hi + np - 1) % np;
+    hi %= np;
+    double t0 = pol[lo].first, t1 = pol[hi].first;
+    if (t0 > th) t0 -= 2.0 * M_PI;
+    if (t1 < th) t1 += 2.0 * M_PI;
+    const double f = t1 > t0 ? (th - t0) / (t1 - t0) : 0.0;
+    rad[k] = (float)(pol[lo].second + f * (pol[hi].second - pol[lo].second));
+  }
+  *ac = (float)c;
+  return true;
+}
+}  // namespace
+
+extern "C" {
+
+kh_status kh_mlp_image(kh_ctx* ctx, const kh_mlp* net, const kh_camera* cam, const kh_mlp_fallback* fb, float* out,
                        int32_t* fallback_ids, int32_t* fallback_count, void* stream) {
   if (!ctx) return KH_EINVAL;
   g_skip_ptr_query = capturing(stream);
@@ -741,7 +858,10 @@ kh_status kh_mlp_image(kh_ctx* ctx, const kh_mlp* net, const kh_camera* cam, flo
     return fail(ctx, KH_EINVAL, "camera: need width, height >= 1 and |a| <= 1");
   const int64_t m = int64_t(cam->width) * cam->height;
   if (m >= (int64_t(1) << 31)) return fail(ctx, KH_EINVAL, "image too large");
-  if (!(tau >= 0.0f && tau < 0.5f)) return fail(ctx, KH_EINVAL, "tau must be in [0, 0.5)");
+  if (!fb) return fail(ctx, KH_EINVAL, "fallback rules are required");
+  if (!(fb->tau >= 0.0f && fb->tau < 0.5f)) return fail(ctx, KH_EINVAL, "tau must be in [0, 0.5)");
+  if (!(fb->shadow_band >= 0.0f && fb->shadow_band < 1e3f) || !(fb->r_min >= 0.0f && fb->r_min < 1e6f))
+    return fail(ctx, KH_EINVAL, "shadow_band and r_min must be finite and >= 0");
   const void* ps[] = {out, fallback_ids, fallback_count};
   for (const void* q : ps)
     if (!q || !device_ok(q)) return fail(ctx, KH_EINVAL, "out, fallback_ids, fallback_count must be device memory");
@@ -755,7 +875,10 @@ kh_status kh_mlp_image(kh_ctx* ctx, const kh_mlp* net, const kh_camera* cam, flo
   A.m = m;
   A.cam = *cam;
   A.y = out;
-  A.tau = tau;
+  A.tau = fb->tau;
+  A.r_min = fb->r_min;
+  A.crit_band = 0.0f;
+  if (fb->shadow_band > 0.0f && critical_curve(cam->a, cam->incl, &A.crit_ac, A.crit_r)) A.crit_band = fb->shadow_band;
   A.fb_ids = fallback_ids;
   A.fb_count = fallback_count;
   hipLaunchKernelGGL(k_mlp_fwd_split<1>, dim3((unsigned)((m + 4 * RAYS - 1) / (4 * RAYS))), dim3(256), 0, strm, A);
@@ -782,7 +905,8 @@ kh_status kh_mlp_targets(kh_ctx* ctx, const kh_state* st, const double* alpha, c
 }
 
 kh_status kh_mlp_grad(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batch, const float* x, const float* t,
-                      const uint8_t* mask, int32_t b, float* grad, float* loss, void* stream) {
+                      const uint8_t* mask, int32_t b, const kh_mlp_loss_w* lw, float* grad, float* loss,
+                      void* stream) {
   if (!ctx) return KH_EINVAL;
   g_skip_ptr_query = capturing(stream);
   kh_status s = check_net(ctx, net, false);
@@ -792,15 +916,15 @@ kh_status kh_mlp_grad(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_ba
   if ((s = set_device(ctx)) != KH_OK) return s;
   hipStream_t strm = (hipStream_t)stream;
   Work w;
-  if ((s = grad_pass(ctx, net, work, max_batch, x, t, mask, b, loss, strm, &w)) != KH_OK) return s;
+  if ((s = grad_pass(ctx, net, work, max_batch, x, t, mask, b, lw, loss, strm, &w)) != KH_OK) return s;
   hipLaunchKernelGGL(k_mlp_reduce, dim3((NP + 255) / 256), dim3(256), 0, strm, w.part, grad);
   KH_HIP(ctx, hipGetLastError());
   return KH_OK;
 }
 
 kh_status kh_mlp_train_step(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batch, const float* x,
-                            const float* t, const uint8_t* mask, int32_t b, const kh_adam* opt, float* loss,
-                            void* stream) {
+                            const float* t, const uint8_t* mask, int32_t b, const kh_mlp_loss_w* lw,
+                            const kh_adam* opt, float* loss, void* stream) {
   if (!ctx) return KH_EINVAL;
   g_skip_ptr_query = capturing(stream);
   kh_status s = check_net(ctx, net, true);
@@ -809,7 +933,7 @@ kh_status kh_mlp_train_step(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t 
   if ((s = set_device(ctx)) != KH_OK) return s;
   hipStream_t strm = (hipStream_t)stream;
   Work w;
-  if ((s = grad_pass(ctx, net, work, max_batch, x, t, mask, b, loss, strm, &w)) != KH_OK) return s;
+  if ((s = grad_pass(ctx, net, work, max_batch, x, t, mask, b, lw, loss, strm, &w)) != KH_OK) return s;
   hipLaunchKernelGGL(k_mlp_adam, dim3((NP + 255) / 256), dim3(256), 0, strm, net->params, net->adam_m, net->adam_v,
                      w.part, *opt, reinterpret_cast<__bf16*>(net->wb), reinterpret_cast<__bf16*>(net->wbt));
   KH_HIP(ctx, hipGetLastError());

@@ -52,7 +52,8 @@ def _batch(n):
 def test_forward_matches_reference(ctx):
     """Raw outputs for 1000 rays (31 full waves and a ragged one), with
     nonzero biases in every layer, equal the FP64 reference with BF16 storage
-    of weights and activations, to the FP32 accumulation-order level."""
+    of weights and activations, to the FP32 accumulation-order level: every
+    output within 2e-3 of the largest |y|."""
     say("mlp forward")
     p = _random_biases(S.init_params(11), 21)
     net = K.Mlp(p, train=False)
@@ -65,16 +66,18 @@ def test_forward_matches_reference(ctx):
     err = np.abs(got - want).max() / np.abs(want).max()
     col = np.abs(got - want).max(axis=0) / np.abs(want).max(axis=0)
     say(f"  max abs err / max |y| = {err:.2e}; per output {np.array2string(col, precision=2)}")
-    assert err < 2e-2
+    # element by element: observed 7.6e-4 / 1.2e-3 with the inputs as one / two
+    # BF16 terms (FP32 accumulation order against FP64, BF16 rounding flips)
+    assert err < 2e-3
     # and the plain FP64 network is close too (BF16 storage costs ~1e-2)
     plain, _ = M.forward(p.astype(np.float64), x.astype(np.float64))
     assert np.abs(got - plain).max() / np.abs(plain).max() < 5e-2
 
 
 def test_gradient_matches_reference(ctx):
-    """kh_mlp_grad on a 512-ray batch against the FP64 reference gradient
-    (BF16 storage of weights and activations; the GPU also stores the
-    back-propagated errors as BF16)."""
+    """kh_mlp_grad on a 512-ray batch with unequal loss weights against the
+    FP64 reference gradient (BF16 storage of weights and activations; the GPU
+    also stores the back-propagated errors as BF16)."""
     say("mlp gradient")
     p = _random_biases(S.init_params(12) * 0.7, 23)
     net = K.Mlp(p, train=True)
@@ -83,26 +86,32 @@ def test_gradient_matches_reference(ctx):
     work = torch.empty(K.kh_mlp_work_bytes(512), dtype=torch.uint8, device="cuda")
     grad = torch.empty(K.MLP_NPARAMS, dtype=torch.float32, device="cuda")
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    weights = (0.5, 2.0, 16.0, 0.25)  # (r, phi, g, capture): every term weighted differently
     ctx.kh_mlp_grad(net, work, 512, torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(),
-                    torch.from_numpy(mask).cuda(), 512, grad, loss)
+                    torch.from_numpy(mask).cuda(), 512, grad, loss, loss_w=weights)
     g = grad.cpu().numpy().astype(np.float64)
     lw, gw = M.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64), mask,
-                             bf16_storage=True)
+                             bf16_storage=True, weights=weights)
     rel = np.linalg.norm(g - gw) / np.linalg.norm(gw)
     cos = g @ gw / (np.linalg.norm(g) * np.linalg.norm(gw))
     say(f"  loss {loss.item():.6f} vs {lw:.6f}; grad rel err {rel:.2e}, cosine {cos:.6f}")
-    assert loss.item() == pytest.approx(lw, rel=1e-2)
-    assert rel < 3e-2 and cos > 0.9995
-    # every layer's weight and bias block agrees in direction
+    assert loss.item() == pytest.approx(lw, rel=1e-3)
+    assert rel < 5e-3 and cos > 0.99999
+    # element by element in every weight and bias block: each entry within
+    # 1e-2 of the block's largest |g| (observed <= 5.2e-3 with these weights,
+    # 1.8e-3 with unit weights: BF16 storage of the back-propagated errors,
+    # 2^-8 relative per rounding), and within 1e-1 of |g| + max|g| / 10
     off = 0
     for nin, nout in M.LAYERS:
         for size in (nin * nout, nout):
             a, b = g[off:off + size], gw[off:off + size]
-            say(f"  block {nin}x{nout} size {size}: max |dg| / max |g| = "
-                f"{np.abs(a - b).max() / max(np.abs(b).max(), 1e-300):.2e}, "
-                f"max |dg| / (|g| + max|g|/10) = {np.max(np.abs(a - b) / (np.abs(b) + 0.1 * np.abs(b).max())):.2e}")
-            if np.linalg.norm(b) > 0:
-                assert a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300) > 0.995, (nin, nout, size)
+            scale = np.abs(b).max()
+            worst = np.abs(a - b).max() / max(scale, 1e-300)
+            mixed = np.max(np.abs(a - b) / (np.abs(b) + 0.1 * scale))
+            say(f"  block {nin}x{nout} size {size}: max |dg| / max |g| = {worst:.2e}, "
+                f"max |dg| / (|g| + max|g|/10) = {mixed:.2e}")
+            assert scale > 0, (nin, nout, size)
+            assert worst < 1e-2 and mixed < 1e-1, (nin, nout, size)
             off += size
 
 
@@ -141,7 +150,7 @@ def test_image_kernel_decodes_forward_and_lists_fallback(ctx):
         say(f"  tau {tau}: {k} fallback pixels")
         assert np.array_equal(listed, want)
     ref, _ = M.forward(p.astype(np.float64), x.astype(np.float64), bf16_storage=True)
-    assert np.abs(raw - ref).max() / np.abs(ref).max() < 2e-2
+    assert np.abs(raw - ref).max() / np.abs(ref).max() < 2e-3
 
 
 def test_image_kernel_full_size_sampled(ctx):
@@ -170,13 +179,23 @@ def test_image_kernel_full_size_sampled(ctx):
     be = cam.beta_min + (row + 0.5) * (cam.beta_max - cam.beta_min) / cam.height
     x = np.stack([al, be, np.full(len(pix), cam.a), np.full(len(pix), cam.incl)], axis=1).astype(np.float32)
     ref, _ = M.forward(p.astype(np.float64), x.astype(np.float64), bf16_storage=True)
-    # compare in the raw (pre-decode) outputs: invert the decode of the kernel
+    # compare r, phi and g in the raw (pre-decode) outputs, inverting the
+    # kernel's decode, and the capture probability as a probability (the
+    # logit of an FP32 probability near 0 or 1 is not recoverable)
     got = img[pix]
-    raw = np.stack([(np.log(got[:, 0]) - 2) / 2, got[:, 1] / np.pi, (got[:, 2] - 0.8) / 0.3,
-                    np.log(got[:, 3] / (1 - got[:, 3]))], axis=1)
-    err = np.abs(raw - ref).max() / np.abs(ref).max()
-    say(f"  sampled raw-output error / max |y| = {err:.2e}")
-    assert err < 2e-2
+    raw = np.stack([(np.log(got[:, 0]) - 2) / 2, got[:, 1] / np.pi, (got[:, 2] - 0.8) / 0.3], axis=1)
+    scale = np.abs(ref).max()
+    err = np.abs(raw - ref[:, :3]).max() / scale
+    p_ref = 1 / (1 + np.exp(-ref[:, 3]))
+    err_p = np.abs(got[:, 3] - p_ref).max()
+    say(f"  sampled raw-output error / max |y| = {err:.2e}; capture probability error {err_p:.2e}")
+    # observed 2.8e-3 (inputs as one BF16 term) and 4.5e-3 (two terms) on this
+    # network: a BF16 activation that the FP32 sum order puts on the other
+    # side of a rounding boundary differs by one BF16 step (2^-8 relative),
+    # and such flips add up over the four hidden layers of this random network
+    assert err < 6e-3
+    # sigmoid' <= 1/4: a logit error of 6e-3 max|y| moves p by at most a quarter of that
+    assert err_p < 1.5e-3 * scale + 1e-6
     pc = img[:, 3]
     # a second threshold that lists about half of the image
     tau2 = float(np.quantile(np.minimum(pc, 1 - pc), 0.5))
@@ -195,7 +214,69 @@ def test_image_kernel_full_size_sampled(ctx):
         assert np.array_equal(np.sort(listed), want)
 
 
-def test_pixel_init_targets_and_image_from_state(ctx):
+def _critical_distance(cam, al, be):
+    """Signed distance (M) of image points from the camera's critical curve,
+    from Bardeen's closed form (tests/closed_forms.py), measured along the
+    ray from the curve's centre: the curve's radius in the direction of the
+    point by interpolation over a dense sampling of the photon-orbit radius."""
+    from closed_forms import bardeen_alpha, bardeen_beta2, r_prograde_photon, r_retrograde_photon
+
+    rs = np.linspace(r_prograde_photon(cam.a), r_retrograde_photon(cam.a), 20001)
+    b2 = np.array([bardeen_beta2(r, cam.a, cam.incl) for r in rs])
+    A = np.array([bardeen_alpha(r, cam.a, cam.incl) for r in rs])[b2 >= 0]
+    B = np.sqrt(b2[b2 >= 0])
+    A, B = np.concatenate([A, A]), np.concatenate([B, -B])
+    c = 0.5 * (A.max() + A.min())
+    th, rad = np.arctan2(B, A - c), np.hypot(A - c, B)
+    o = np.argsort(th)
+    r_curve = np.interp(np.arctan2(be, al - c), th[o], rad[o], period=2 * np.pi)
+    return np.hypot(al - c, be) - r_curve
+
+
+def test_image_kernel_fallback_rules(ctx):
+    """The image kernel's two geometric fallback rules on a 67x61 camera at
+    a = 0.9, 45 deg over [-8, 8] x [-7, 7] (the critical curve crosses the
+    field): with the capture band closed, the listed pixels are exactly those
+    within shadow_band of the critical curve (distance from Bardeen's closed
+    form on the host) or with a decoded crossing radius below r_min and
+    p <= 1/2; pixels within 2e-3 M of the band's edge may go either way."""
+    say("mlp image fallback rules")
+    p = _random_biases(S.init_params(16), 27)
+    net = K.Mlp(p, train=False)
+    ctx.kh_mlp_sync(net)
+    cam = W.Camera(0.9, 1000.0, 45.0, -8.0, 8.0, -7.0, 7.0, 67, 61)
+    n = cam.n
+    col, row = np.arange(n) % cam.width, np.arange(n) // cam.width
+    al = cam.alpha_min + (col + 0.5) * (cam.alpha_max - cam.alpha_min) / cam.width
+    be = cam.beta_min + (row + 0.5) * (cam.beta_max - cam.beta_min) / cam.height
+    dist = _critical_distance(cam, al, be)
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    ids = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.kh_mlp_image(net, S.camera_struct(cam), 0.49999, out, ids, cnt)  # capture band alone: ~no pixel
+    img = out.cpu().numpy().astype(np.float64)
+    pc, rr = img[:, 3], img[:, 0]
+    base = (pc > 0.49999) & (pc < 1 - 0.49999)
+    r_min = float(np.median(rr[pc <= 0.5]))
+    for band, rmin in ((0.4, 0.0), (0.0, r_min), (0.25, r_min)):
+        ids.fill_(-1)
+        ctx.kh_mlp_image(net, S.camera_struct(cam), 0.49999, out, ids, cnt, shadow_band=band, r_min=rmin)
+        torch.cuda.synchronize()
+        k = int(cnt.item())
+        listed = np.zeros(n, bool)
+        listed[ids.cpu().numpy()[:k]] = True
+        assert len(np.unique(ids.cpu().numpy()[:k])) == k
+        want = base | ((pc <= 0.5) & (rr < rmin))
+        edge = np.zeros(n, bool)
+        if band > 0:
+            want |= np.abs(dist) < band
+            edge = np.abs(np.abs(dist) - band) < 2e-3
+        say(f"  shadow_band {band}, r_min {rmin:.3f}: {k} listed, {int(want.sum())} expected, "
+            f"{int(edge.sum())} at the band's edge")
+        assert np.array_equal(listed[~edge], want[~edge])
+        assert edge.sum() < 0.01 * n
+        assert 0 < k < n
+
     """The surrogate pipeline's data calls on a ragged 23x19 camera:
     kh_init_rays_pixels gives bitwise the kh_init_rays states of the listed
     pixels; after integration, kh_image_from_state (in place and scattered
@@ -271,6 +352,36 @@ def test_forward_single_ray_and_one_past_a_block(ctx):
         assert torch.equal(y, full[:m])
 
 
+def test_padding_stays_zero_after_training(ctx):
+    """The BF16 copies pad layer 0 to 16 inputs and layer 4 to 32 outputs
+    (the matrix-core tile sizes); after Adam steps with nonzero gradients the
+    padding is still exactly zero in the forward copy ([256][16] at 0, whose
+    columns 4..7 repeat W0 for the low BF16 terms of the inputs; [32][256] at
+    200,704) and in the transposed copy of layer 4 ([256][32] at 196,608), and
+    the FP32 master weights changed."""
+    say("mlp padding after training steps")
+    p = _random_biases(S.init_params(15), 26)
+    net = K.Mlp(p, train=True)
+    ctx.kh_mlp_sync(net)
+    x, t, mask = _batch(512)
+    work = torch.empty(K.kh_mlp_work_bytes(512), dtype=torch.uint8, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    xd, td, md = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), torch.from_numpy(mask).cuda()
+    for step in range(1, 6):
+        ctx.kh_mlp_train_step(net, work, 512, xd, td, md, 512, K.kh_adam(1e-2, 0.9, 0.999, 1e-8, step), loss)
+    torch.cuda.synchronize()
+    assert not np.array_equal(net.params.cpu().numpy(), p.astype(np.float32))
+    wb = net.wb.cpu().numpy()
+    wbt = net.wbt.cpu().numpy()
+    w0 = wb[:256 * 16].reshape(256, 16)
+    w4 = wb[200704:200704 + 32 * 256].reshape(32, 256)
+    w4t = wbt[196608:196608 + 256 * 32].reshape(256, 32)
+    assert (w0[:, 8:] == 0).all() and (w0[:, :4] != 0).any()
+    assert np.array_equal(w0[:, 4:8], w0[:, :4])
+    assert (w4[4:] == 0).all() and (w4[:4] != 0).any()
+    assert (w4t[:, 4:] == 0).all() and (w4t[:, :4] != 0).any()
+
+
 def test_training_and_fallback_image(ctx):
     """Train on 2^18 integrated rays for 600 steps, then render a 256x256 image
     at a = 0.9, i = 45 deg: the loss falls, the fallback integrates a minority
@@ -290,3 +401,37 @@ def test_training_and_fallback_image(ctx):
     say(f"  fallback fraction {tm['fallback_fraction']:.3f}; error {err}")
     assert tm["fallback_fraction"] < 0.6
     assert err["capture_mismatch"] < 0.02
+
+
+@pytest.mark.timeout(300)
+def test_surrogate_beats_integrator_at_fixed_error(ctx):
+    """What the trained network gains: trained as the benchmark trains it
+    (1e7 integrated rays, 40,000 Adam steps with the library's loss weights),
+    the surrogate renders the 2048^2 image at a = 0.9, 45 deg with fallback
+    (capture band 0.2, shadow-edge band 0.3 M) within the stated image error
+    of the integrator's own image -- capture mismatch <= 1e-4 of the pixels
+    and p99 |dg| <= 1e-3 where both have a crossing -- in less time than the
+    integrator takes for that image."""
+    say("surrogate against the plain integrator at the fixed image error")
+    sur = S.Surrogate(ctx, seed=0, max_batch=8192)
+    x, t, mask, _ = sur.make_data(10_000_000)
+    sur.train(x, t, mask, steps=40000, batch=8192, lr=2e-3, loss_w=S.LOSS_WEIGHTS)
+    del x, t, mask
+    cam = W.surrogate_eval_camera(side=2048)
+    S.integrate_image(ctx, cam)
+    t_int = []
+    for _ in range(2):
+        ref, dt = S.integrate_image(ctx, cam)
+        t_int.append(dt)
+    sur.render(cam, 0.2, shadow_band=0.3)
+    t_sur = []
+    for _ in range(2):
+        img, tm = sur.render(cam, 0.2, shadow_band=0.3)
+        t_sur.append(tm["total_s"])
+    err = S.image_error(img, ref)
+    speedup = min(t_int) / min(t_sur)
+    say(f"  integrator {min(t_int) * 1e3:.2f} ms, surrogate {min(t_sur) * 1e3:.2f} ms (speedup {speedup:.2f}), "
+        f"fallback {tm['fallback_fraction']:.4f}; error {err}")
+    assert err["capture_mismatch"] <= 1e-4
+    assert err["g_abs_p99"] <= 1e-3
+    assert speedup > 1.0

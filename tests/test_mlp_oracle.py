@@ -21,15 +21,17 @@ def test_parameter_count():
     assert M.NPARAMS == 199684
 
 
-def test_gradient_matches_central_differences():
+@pytest.mark.parametrize("weights", [(1.0, 1.0, 1.0, 1.0), (0.5, 2.0, 16.0, 0.25)])
+def test_gradient_matches_central_differences(weights):
     p = M.init_params(3) * 0.5
     x, t, mask = _batch(16)
-    _, g = M.loss_and_grad(p, x, t, mask)
+    _, g = M.loss_and_grad(p, x, t, mask, weights=weights)
     idx = np.concatenate([rng.integers(0, 1280, 6), rng.integers(1280, 198656, 10), rng.integers(198656, M.NPARAMS, 6)])
     for i in idx:
         e = np.zeros_like(p)
         e[i] = 1e-6
-        fd = (M.loss_and_grad(p + e, x, t, mask)[0] - M.loss_and_grad(p - e, x, t, mask)[0]) / 2e-6
+        fd = (M.loss_and_grad(p + e, x, t, mask, weights=weights)[0] -
+              M.loss_and_grad(p - e, x, t, mask, weights=weights)[0]) / 2e-6
         assert fd == pytest.approx(g[i], rel=1e-4, abs=1e-9), i
 
 
@@ -42,6 +44,11 @@ def test_loss_definition_on_a_zero_network():
     loss, _ = M.loss_and_grad(p, x, t, mask)
     want = np.mean([1 + 4 + 9 + np.log(2), 0.25 + 0 + np.log(2), 0 + np.log(2), np.log(2)])
     assert loss == pytest.approx(want, rel=1e-12)
+    # each weight scales its own term: (r, phi, g, capture) = (2, 3, 5, 7)
+    loss_w, _ = M.loss_and_grad(p, x, t, mask, weights=(2.0, 3.0, 5.0, 7.0))
+    want_w = np.mean([2 * 1 + 3 * 4 + 5 * 9 + 7 * np.log(2), 2 * 0.25 + 0 + 7 * np.log(2), 0 + 7 * np.log(2),
+                      7 * np.log(2)])
+    assert loss_w == pytest.approx(want_w, rel=1e-12)
 
 
 def test_bf16_rounding():
