@@ -219,9 +219,12 @@ kh_status kh_init_rays(kh_ctx *ctx, const kh_camera *cams, int32_t n_cams, kh_st
 kh_status kh_init_rays_list(kh_ctx *ctx, const double *spin, const double *incl, const double *alpha,
                             const double *beta, double r_obs, kh_state *st, void *stream);
 
-/* Geodesics from positions x3 [3][n] and spins [n] (device).  KH_TIMELIKE: v3
+/* Geodesics from positions x3 [3][n] and spins [n] (device): the initial data
+ * of Sec. 3.2's time-like orbits (a particle given by its position and
+ * coordinate velocity) and of null rays started anywhere.  KH_TIMELIKE: v3
  * [3][n] is the coordinate velocity dx^i/dt and u^0 = 1/sqrt(-g_ab v^a v^b) with
- * v^0 = 1 (status KH_FAILED where that norm is not negative).  KH_NULL: v3 is
+ * v^0 = 1, the normalisation of the four-velocity in the metric def:CKS
+ * (status KH_FAILED where that norm is not negative).  KH_NULL: v3 is
  * the spatial momentum and k^0 the future root of the null condition.
  * st->order gets the natural order.  If st->perm is set, the call also writes
  * a per-geodesic schedule, longest expected integration first, so that the
@@ -237,7 +240,11 @@ kh_status kh_init_geodesics(kh_ctx *ctx, int32_t kind, const double *spin, const
                             kh_state *st, void *stream);
 
 /* Integrate every geodesic whose status is KH_ACTIVE or KH_MAX_STEPS until it
- * terminates or takes max_steps accepted steps in this call.  Asynchronous; no
+ * terminates or takes max_steps accepted steps in this call: the geodesic
+ * equation eq:geo with its right-hand side in the form of eq:opt0 / eq:opti
+ * (Sec. 2.1), stepped by RK4 (Sec. 3) or the Dormand-Prince 5(4) pair, in the
+ * affine parameter or (KH_DOPRI5_T) in coordinate time as in eq:geo_t
+ * (Sec. 2.2), terminated as in Sec. 4's benchmark (horizon, escape radius).  Asynchronous; no
  * allocation and no host synchronisation.  Re-entrant: a paused state resumes
  * exactly (bitwise) where it stopped.  Persistent kernel: each 64-lane wave
  * takes rays from a global counter and refills retired lanes, in the order of
