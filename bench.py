@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (256 CU x 64 lanes x 2 flop x 2.4 GHz)
-FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (wave64 FP32 instructions issue in 2 cycles)
+FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32, published (packed FP32; non-packed FMAs issue at the FP64 rate)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -332,9 +332,9 @@ def elapse_extra(ctx, K, W, torch, reps=5):
                 del fs, y0
     out["workload"] = ("a=0.999, 1024x1024 image at r=1024 M, 60 deg, [-12,12]^2; one launch of 1024 RK4 steps "
                        "(h = r/256) per ray; shortest of 5 launches")
-    out["peak_note"] = ("vector peaks FP32 157.3 and FP64 78.6 TFLOP/s; the FP32 kernels, built without packed "
-                        "FP32, issue 0.33 VALU instructions per SIMD cycle (rocprofv3), above the 0.25 a 4-cycle "
-                        "FP32 issue would allow, so 157.3 is their ceiling")
+    out["peak_note"] = ("vector peaks FP32 157.3 (published, packed FP32) and FP64 78.6 TFLOP/s; the FP32 "
+                        "kernels are built without packed FP32, whose FMAs issue at the FP64 rate, so their "
+                        "arithmetic is held near 78.6; alg_frac_fp_vector_peak uses 157.3 for FP32")
     return out
 
 
