@@ -276,6 +276,12 @@ def test_image_kernel_fallback_rules(ctx):
         assert np.array_equal(listed[~edge], want[~edge])
         assert edge.sum() < 0.01 * n
         assert 0 < k < n
+    # argument errors come before any launch and leave the outputs alone
+    ids.fill_(-1)
+    for tau, band, rmin in ((0.5, 0.0, 0.0), (-0.1, 0.0, 0.0), (0.1, -1.0, 0.0), (0.1, 0.0, float("nan"))):
+        with pytest.raises(K.KerrHipError):
+            ctx.kh_mlp_image(net, S.camera_struct(cam), tau, out, ids, cnt, shadow_band=band, r_min=rmin)
+    assert (ids.cpu().numpy() == -1).all()
 
     """The surrogate pipeline's data calls on a ragged 23x19 camera:
     kh_init_rays_pixels gives bitwise the kh_init_rays states of the listed
