@@ -372,10 +372,19 @@ def surrogate_extra(ctx, K, W, torch, args):
     # mismatches and p99 |dg| <= 1e-3; None when no setting meets both
     ok = [c for c in curve if c["capture_mismatch"] <= 1e-4 and c["g_abs_p99"] <= 1e-3]
     best = max(ok, key=lambda c: c["speedup"]) if ok else None
+    # the integrator judging the image without the full reference: an audit
+    # of 2^17 random pixels at the fixed-error setting, against the full error
+    audit = None
+    if best is not None:
+        img, _ = sur.render(cam, best["tau"], shadow_band=best["shadow_band"], r_min=best["r_min"])
+        audit = sur.audit(cam, img, 1 << 17, seed=1)
+        log(f"surrogate audit of {audit['audit_rays']} pixels ({audit['audit_s'] * 1e3:.2f} ms): capture mismatch "
+            f"{audit['capture_mismatch']:.2e}, |dg| p99 {audit['g_abs_p99']:.2e} (full image "
+            f"{best['capture_mismatch']:.2e}, {best['g_abs_p99']:.2e})")
     return dict(train_rays=args.surrogate_rays, data_s=t_data, train_steps=args.surrogate_steps, batch=8192,
                 loss_weights=dict(zip(("r", "phi", "g", "capture"), S.LOSS_WEIGHTS)), train_s=t_train,
                 loss_history=hist, integrator_s=t_int, image=f"{cam.width}x{cam.height}", curve=curve,
-                at_fixed_error=best, fixed_error_met=best is not None,
+                at_fixed_error=best, fixed_error_met=best is not None, audit_at_fixed_error=audit,
                 fixed_error="capture-flag mismatch <= 1e-4 of pixels and p99 |dg| <= 1e-3 on pixels where both "
                             "images have a crossing; r and phi errors stated alongside")
 

@@ -146,6 +146,30 @@ class Surrogate:
                          fallback_fraction=n_fb / (cam.width * cam.height))
 
 
+    def audit(self, cam, img, n: int, seed: int = 0, params=None):
+        """The integrator judging a rendered image without a full reference:
+        n pixels drawn uniformly (seeded) are integrated and compared with the
+        image, pixels that went to the fallback included (there the error is
+        zero, as in the full comparison).  Returns the estimated image error
+        (image_error's fields on the sample), the audit's run time and n."""
+        p = params or integrator_params()
+        npix = cam.width * cam.height
+        n = min(int(n), npix)
+        pix = np.sort(np.random.default_rng(seed).choice(npix, n, replace=False)).astype(np.int32)
+        dev = torch.from_numpy(pix).cuda()
+        ref = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = State(n, k_cross=1, constants=False)
+        self.ctx.kh_init_rays_pixels(camera_struct(cam), dev, st)
+        self.ctx.kh_integrate(p, st)
+        self.ctx.kh_image_from_state(st, None, ref)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        est = image_error(img[dev.long()], ref)
+        return dict(est, audit_rays=n, audit_s=dt)
+
+
 def integrate_image(ctx: Context, cam, params=None):
     """The integrator's image of a camera in the surrogate's format, and its time."""
     p = params or integrator_params()

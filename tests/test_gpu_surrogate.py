@@ -417,7 +417,8 @@ def test_surrogate_beats_integrator_at_fixed_error(ctx):
     (capture band 0.2, shadow-edge band 0.3 M) within the stated image error
     of the integrator's own image -- capture mismatch <= 1e-4 of the pixels
     and p99 |dg| <= 1e-3 where both have a crossing -- in less time than the
-    integrator takes for that image."""
+    integrator takes for that image; and an audit of a random pixel sample
+    estimates that error without the full reference."""
     say("surrogate against the plain integrator at the fixed image error")
     sur = S.Surrogate(ctx, seed=0, max_batch=8192)
     x, t, mask, _ = sur.make_data(10_000_000)
@@ -441,3 +442,11 @@ def test_surrogate_beats_integrator_at_fixed_error(ctx):
     assert err["capture_mismatch"] <= 1e-4
     assert err["g_abs_p99"] <= 1e-3
     assert speedup > 1.0
+    # an audit of 2^16 random pixels (1.6 % of the image) estimates the same
+    # error without the full reference image: its p99 |dg| within 15 % of the
+    # full image's (observed a few per cent), its capture mismatch at most a
+    # few pixels
+    aud = sur.audit(cam, img, 1 << 16, seed=3)
+    say(f"  audit of {aud['audit_rays']} pixels ({aud['audit_s'] * 1e3:.2f} ms): {aud}")
+    assert abs(aud["g_abs_p99"] / err["g_abs_p99"] - 1) < 0.15
+    assert aud["capture_mismatch"] <= 1e-4 + 3.0 / aud["audit_rays"]
