@@ -104,7 +104,7 @@ __device__ inline f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c)
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-constexpr int kCritBins = 128;  // angle bins of the critical-curve table
+constexpr int kCritBins = 256;  // angle bins of the critical-curve table
 
 struct FwdArgs {
   const float* params;

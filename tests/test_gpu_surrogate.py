@@ -221,6 +221,8 @@ def _critical_distance(cam, al, be):
     point by interpolation over a dense sampling of the photon-orbit radius."""
     from closed_forms import bardeen_alpha, bardeen_beta2, r_prograde_photon, r_retrograde_photon
 
+    if cam.a == 0.0:  # Schwarzschild: the circle of radius sqrt(27)
+        return np.hypot(al, be) - np.sqrt(27.0)
     rs = np.linspace(r_prograde_photon(cam.a), r_retrograde_photon(cam.a), 20001)
     b2 = np.array([bardeen_beta2(r, cam.a, cam.incl) for r in rs])
     A = np.array([bardeen_alpha(r, cam.a, cam.incl) for r in rs])[b2 >= 0]
@@ -282,6 +284,42 @@ def test_image_kernel_fallback_rules(ctx):
         with pytest.raises(K.KerrHipError):
             ctx.kh_mlp_image(net, S.camera_struct(cam), tau, out, ids, cnt, shadow_band=band, r_min=rmin)
     assert (ids.cpu().numpy() == -1).all()
+
+
+@pytest.mark.parametrize("a,incl", [(0.0, 60.0), (-0.7, 30.0), (0.998, 80.0)])
+def test_image_kernel_shadow_band_other_cameras(ctx, a, incl):
+    """The shadow-edge rule for a Schwarzschild hole (circle of radius
+    sqrt(27)), a negative spin (the mirror image in alpha) and a near-extremal,
+    nearly edge-on camera: the listed pixels are those within the band of the
+    critical curve, up to pixels at the band's edge."""
+    say(f"mlp shadow band, a = {a}, incl = {incl}")
+    p = _random_biases(S.init_params(17), 28)
+    net = K.Mlp(p, train=False)
+    ctx.kh_mlp_sync(net)
+    cam = W.Camera(a, 1000.0, incl, -8.0, 8.0, -7.0, 7.0, 61, 53)
+    n = cam.n
+    col, row = np.arange(n) % cam.width, np.arange(n) // cam.width
+    al = cam.alpha_min + (col + 0.5) * (cam.alpha_max - cam.alpha_min) / cam.width
+    be = cam.beta_min + (row + 0.5) * (cam.beta_max - cam.beta_min) / cam.height
+    dist = _critical_distance(cam, al, be)
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    ids = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    band = 0.35
+    ctx.kh_mlp_image(net, S.camera_struct(cam), 0.49999, out, ids, cnt, shadow_band=band)
+    torch.cuda.synchronize()
+    pc = out.cpu().numpy()[:, 3].astype(np.float64)
+    k = int(cnt.item())
+    listed = np.zeros(n, bool)
+    listed[ids.cpu().numpy()[:k]] = True
+    want = ((pc > 0.49999) & (pc < 1 - 0.49999)) | (np.abs(dist) < band)
+    # the kernel interpolates the curve's radius linearly over 256 angle bins
+    # (error ~r (2 pi / 256)^2 / 8 < 1e-3 M); pixels that close to the band's
+    # edge may go either way
+    edge = np.abs(np.abs(dist) - band) < 2e-3
+    say(f"  {k} listed, {int(want.sum())} expected, {int(edge.sum())} at the band's edge")
+    assert np.array_equal(listed[~edge], want[~edge])
+    assert 0 < k < n
 
     """The surrogate pipeline's data calls on a ragged 23x19 camera:
     kh_init_rays_pixels gives bitwise the kh_init_rays states of the listed
