@@ -41,7 +41,8 @@ typedef struct {
   float *params;   /* [KH_MLP_NPARAMS] FP32 master weights */
   float *adam_m;   /* [KH_MLP_NPARAMS] Adam first moment (training only, else NULL) */
   float *adam_v;   /* [KH_MLP_NPARAMS] Adam second moment (training only, else NULL) */
-  uint16_t *wb;    /* [KH_MLP_WB_ELEMS] BF16 copies in the forward layout */
+  uint16_t *wb;    /* [KH_MLP_WB_ELEMS] BF16 copies in the forward layout (per layer 16-input
+                      blocks [padded rows][16]; written by kh_mlp_sync and the training step) */
   uint16_t *wbt;   /* [KH_MLP_WBT_ELEMS] BF16 transposed copies (training only, else NULL) */
 } kh_mlp;
 

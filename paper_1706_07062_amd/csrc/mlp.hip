@@ -1,15 +1,16 @@
 // mlp.hip -- the surrogate network (include/kerrhip_mlp.h) on the BF16 matrix cores.
 //
 // Every product is written as D^T = W X^T: the weight tile is the MFMA A
-// operand (32 output features x 16 inputs, read straight from L2 as 16-byte
-// rows of the [out][in] BF16 copy) and the activations are the B operand
+// operand (32 output features x 16 inputs, read straight from L2: the BF16
+// copy stores each layer in 16-input k-blocks [rows][16], so one k-step's
+// fragment is 1 KB of consecutive memory) and the activations are the B operand
 // (16 inputs x 32 rays).  The 32x32 accumulator then holds, per lane, four
 // consecutive output features of one ray, so bias, SiLU and the BF16 store of
 // the next activation row are one 8-byte write.  In every kernel the waves of
 // a block split each layer's 256 outputs and share the block's activations in
-// LDS rows [ray][feature]: inference (k_mlp_fwd_split) with 128 rays per
-// block, training (k_mlp_fwd_train, k_mlp_bwd_dx) with 32, because a training
-// batch is only a few thousand rays.
+// LDS rows [ray][feature]: inference (k_mlp_fwd_pp) with 128 rays per group
+// of four waves, training (k_mlp_fwd_train, k_mlp_bwd_dx) with 32, because a
+// training batch is only a few thousand rays.
 //
 // MFMA operand layout used (v_mfma_f32_32x32x16_bf16, 64 lanes):
 //   A[i][k]: lane l holds i = l % 32, k = 8 (l / 32) + j, j = 0..7
@@ -56,6 +57,11 @@ constexpr int OFF_WB[5] = {0, 4096, 69632, 135168, 200704};
 // BF16 transposed copies of layers 1..4: [KPAD_l][MPAD_l].
 constexpr int OFF_WBT[5] = {0, 0, 65536, 131072, 196608};
 
+// Element (o, i) of the forward copy of a layer with mpad padded rows: the
+// inputs are cut into 16-wide k-blocks stored one after another, each
+// [mpad][16], so the A fragment of one k-step (32 rows x 16 inputs) is 1 KB of
+// consecutive memory and a wave's weight reads use whole cache lines.
+__host__ __device__ constexpr int wb_index(int mpad, int o, int i) { return (i >> 4) * (mpad * 16) + o * 16 + (i & 15); }
 static_assert(OFF_WB[4] + 32 * 256 == KH_MLP_WB_ELEMS, "forward copy size");
 static_assert(OFF_WBT[4] + 256 * 32 == KH_MLP_WBT_ELEMS, "transposed copy size");
 
@@ -130,112 +136,25 @@ __host__ __device__ inline __bf16* ht_layer(__bf16* ht, int l, int64_t bmax) {
 }
 
 
-// Inference forward as a plain GEMM tiling: a block of four waves carries 128
-// rays; wave w computes outputs 64 w .. 64 w + 63 of every layer for all 128
-// rays (2 x 4 accumulator tiles).  Its weight fragments (its 64 rows) come from
-// L2, one k-step ahead; the activations of the 128 rays sit in LDS rows
-// [ray][feature], read by every wave and rewritten after each layer between
-// two barriers.
+// Image-plane coordinates of the centre of pixel `ray` (< 2^31) of a camera.
+__device__ inline void pixel_coords(const kh_camera& cam, int64_t ray, float& al, float& be) {
+  const uint32_t id = (uint32_t)ray, wdt = (uint32_t)cam.width;
+  const uint32_t row = id / wdt, col = id - row * wdt;
+  al = (float)(cam.alpha_min + (col + 0.5) * (cam.alpha_max - cam.alpha_min) / cam.width);
+  be = (float)(cam.beta_min + (row + 0.5) * (cam.beta_max - cam.beta_min) / cam.height);
+}
+
+// Output layer (256 -> 4, padded to 32 rows) of one ray tile whose
+// activations are the LDS rows rows[32][LDA] (ray = tile's first ray + r), and
+// in camera mode the decode; returns whether the ray goes to the fallback list.
 template <int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_mlp_fwd_split(FwdArgs A) {
-  __shared__ __attribute__((aligned(16))) __bf16 act[4 * RAYS * LDA];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = lane & 31, half = lane >> 5;
-  const int64_t base = (int64_t)blockIdx.x * (4 * RAYS);
-
+__device__ inline bool output_tile(const FwdArgs& A, const __bf16* rows, int64_t ray, int r, int half) {
   const f32x16 zero = {};
-  f32x16 acc[2][4];
-  // The accumulators start from the layer's bias (per lane: outputs
-  // (2 w + tt) 32 + 8 g + 4 half + q of element 4 g + q), so the epilogue is
-  // SiLU and the BF16 store only.
-  auto bias_tiles = [&](const float* bias, f32x16 bt[2]) {
-#pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const f32x4 b = *reinterpret_cast<const f32x4*>(bias + (2 * w + tt) * 32 + 8 * g + 4 * half);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bt[tt][4 * g + q] = b[q];
-      }
-  };
-  f32x16 bt[2];
-  bias_tiles(A.params + OFF_B[0], bt);
-  // layer 0 (K = 4 padded to 16): the B operand of ray tile n is ray base + 32 n + r
-#pragma unroll
-  for (int n = 0; n < 4; ++n) {
-    const int64_t ray = base + 32 * n + r;
-    float f[4] = {0.f, 0.f, 0.f, 0.f};
-    if (ray < A.m) {
-      if (MODE == 1) {
-        const int64_t row = ray / A.cam.width, col = ray % A.cam.width;
-        const float al = (float)(A.cam.alpha_min + (col + 0.5) * (A.cam.alpha_max - A.cam.alpha_min) / A.cam.width);
-        const float be = (float)(A.cam.beta_min + (row + 0.5) * (A.cam.beta_max - A.cam.beta_min) / A.cam.height);
-        norm_features(al, be, (float)A.cam.a, (float)A.cam.incl, f);
-      } else {
-        const f32x4 xv = *reinterpret_cast<const f32x4*>(A.x + ray * 4);
-        norm_features(xv[0], xv[1], xv[2], xv[3], f);
-      }
-    }
-    const bf16x8 bx = input_operand(f, half);
-#pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-      const bf16x8 aw =
-          *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[0] + ((2 * w + tt) * 32 + r) * KPAD[0] + 8 * half);
-      acc[tt][n] = mfma(aw, bx, bt[tt]);
-    }
-  }
-  for (int l = 0; l < 4; ++l) {
-    if (l > 0) {
-      const __bf16* wl = A.wb + (l == 1 ? OFF_WB[1] : l == 2 ? OFF_WB[2] : OFF_WB[3]);
-      const __bf16* arow0 = wl + ((2 * w) * 32 + r) * HID + 8 * half;
-      const __bf16* arow1 = arow0 + 32 * HID;
-      bias_tiles(A.params + (l == 1 ? OFF_B[1] : l == 2 ? OFF_B[2] : OFF_B[3]), bt);
-#pragma unroll
-      for (int tt = 0; tt < 2; ++tt)
-#pragma unroll
-        for (int n = 0; n < 4; ++n) acc[tt][n] = bt[tt];
-      bf16x8 a0 = *reinterpret_cast<const bf16x8*>(arow0);
-      bf16x8 a1 = *reinterpret_cast<const bf16x8*>(arow1);
-      for (int ks = 0; ks < HID / 16; ++ks) {
-        bf16x8 n0 = a0, n1 = a1;
-        if (ks + 1 < HID / 16) {
-          n0 = *reinterpret_cast<const bf16x8*>(arow0 + (ks + 1) * 16);
-          n1 = *reinterpret_cast<const bf16x8*>(arow1 + (ks + 1) * 16);
-        }
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(act + (32 * n + r) * LDA + ks * 16 + 8 * half);
-          acc[0][n] = mfma(a0, bv, acc[0][n]);
-          acc[1][n] = mfma(a1, bv, acc[1][n]);
-        }
-        a0 = n0;
-        a1 = n1;
-      }
-      __syncthreads();  // every wave is done reading this layer's input rows
-    }
-#pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int m0 = (2 * w + tt) * 32 + 8 * g + 4 * half;
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          bf16x4 hv;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) hv[q] = (__bf16)silu(acc[tt][n][4 * g + q]);
-          *reinterpret_cast<bf16x4*>(act + (32 * n + r) * LDA + m0) = hv;
-        }
-      }
-    }
-    __syncthreads();  // the next layer's input rows are complete
-  }
-
-  // output layer (256 -> 4, padded to 32 rows): wave w takes ray tile w
-  const int64_t ray = base + 32 * w + r;
   const bool valid = ray < A.m;
   f32x16 o = zero;
   for (int ks = 0; ks < HID / 16; ++ks) {
-    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(act + (32 * w + r) * LDA + ks * 16 + 8 * half);
-    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + r * HID + ks * 16 + 8 * half);
+    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(rows + r * LDA + ks * 16 + 8 * half);
+    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + wb_index(32, r, ks * 16 + 8 * half));
     o = mfma(aw, bv, o);
   }
   bool unsure = false;
@@ -258,10 +177,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       unsure = pc > A.tau && pc < 1.0f - A.tau;
       unsure = unsure || (pc <= 0.5f && d[0] < A.r_min);
       if (A.crit_band > 0.0f) {
-        const int64_t row = ray / A.cam.width, col = ray % A.cam.width;
-        const float da = (float)(A.cam.alpha_min + (col + 0.5) * (A.cam.alpha_max - A.cam.alpha_min) / A.cam.width) -
-                         A.crit_ac;
-        const float be = (float)(A.cam.beta_min + (row + 0.5) * (A.cam.beta_max - A.cam.beta_min) / A.cam.height);
+        float al, be;
+        pixel_coords(A.cam, ray, al, be);
+        const float da = al - A.crit_ac;
         const float u = (atan2f(be, da) + 3.14159265358979f) * (kCritBins / (2.0f * 3.14159265358979f)) - 0.5f;
         const float fl = floorf(u);
         const float fr = u - fl;
@@ -273,20 +191,193 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       *reinterpret_cast<f32x4*>(A.y + ray * 4) = y;
     }
   }
-  if (MODE == 1) {
-    const unsigned long long mask = __ballot(unsure);
-    if (mask) {
-      const int leader = __ffsll((long long)mask) - 1;
-      int slot = 0;
-      if (lane == leader) slot = atomicAdd(A.fb_count, __popcll(mask));
-      slot = __shfl(slot, leader);
-      if (unsure) {
+  return unsure;
+}
+
+// Barrier for LDS hand-offs only: waits for this wave's LDS operations, not
+// for its global loads or atomics, which stay in flight across it.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Inference forward, ping-pong: a block of eight waves holds two groups of
+// four (waves 0-3 and 4-7; wave w of a block runs on SIMD w % 4, so each SIMD
+// holds one wave of each group).  A group carries 128 rays: its wave w
+// computes outputs 64 w .. 64 w + 63 of every hidden layer for all 128 rays
+// (2 x 4 accumulator tiles), and the group's activations sit in LDS rows
+// [ray][feature], read by its four waves.  A group's work on one batch is eight steps that
+// alternate between the VALU (input features, layer 0 and its SiLU epilogue;
+// the epilogues of layers 1..3) and the matrix cores (the products of layers
+// 1..3; the output layer); group 1 runs one step behind group 0 with a block
+// barrier after every step, so on every SIMD one wave feeds the matrix core
+// while the other issues transcendentals.  The block is persistent: its k-th
+// batch in group g is the 128 rays from 128 (2 (blockIdx + k gridDim) + g).
+// A wave that ends an epilogue requests the first PP_AHEAD k-steps of its next
+// layer's weights, so its products start without waiting for L2; the biases of
+// layers 0..3 sit in LDS and enter as the first k-step's accumulator; the
+// fallback list entry of a tile is written one step after its atomic.
+constexpr int PP_AHEAD = 2;  // weight k-steps in flight
+template <int MODE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_mlp_fwd_pp(FwdArgs A, int32_t nb) {
+  __shared__ __attribute__((aligned(16))) __bf16 act_all[2 * 4 * RAYS * LDA];
+  __shared__ __attribute__((aligned(16))) float bias_s[4 * HID];
+  const int tid = threadIdx.x, grp = tid >> 8, w = (tid >> 6) & 3, lane = tid & 63, r = lane & 31, half = lane >> 5;
+  __bf16* act = act_all + grp * (4 * RAYS * LDA);
+  for (int i = tid; i < 4 * HID; i += 512) {
+    const int l = i / HID;
+    bias_s[i] = A.params[(l == 0 ? OFF_B[0] : l == 1 ? OFF_B[1] : l == 2 ? OFF_B[2] : OFF_B[3]) + i % HID];
+  }
+  __syncthreads();
+
+  f32x16 acc[2][4];
+  bf16x8 ar[PP_AHEAD + 1][2];  // weight fragments of consecutive k-steps (ring)
+  // fallback list entry pending from the last output step
+  unsigned long long p_mask = 0;
+  int p_slot = 0;
+  int64_t p_ray = 0;
+  bool p_unsure = false;
+
+  // accumulator tile tt of a layer's bias (per lane: outputs (2 w + tt) 32 +
+  // 8 g + 4 half + q of element 4 g + q)
+  auto bias_tile = [&](int l, int tt) {
+    f32x16 bt;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const f32x4 b = *reinterpret_cast<const f32x4*>(bias_s + l * HID + (2 * w + tt) * 32 + 8 * g + 4 * half);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bt[4 * g + q] = b[q];
+    }
+    return bt;
+  };
+  auto wrow = [&](int l, int tt) {
+    return A.wb + (l == 1 ? OFF_WB[1] : l == 2 ? OFF_WB[2] : OFF_WB[3]) + wb_index(HID, (2 * w + tt) * 32 + r, 8 * half);
+  };
+  auto prefetch = [&](int l) {
+#pragma unroll
+    for (int q = 0; q < PP_AHEAD; ++q)
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt) ar[q][tt] = *reinterpret_cast<const bf16x8*>(wrow(l, tt) + q * HID * 16);
+  };
+  auto epilogue = [&]() {
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int m0 = (2 * w + tt) * 32 + 8 * g + 4 * half;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          bf16x4 hv;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) hv[q] = (__bf16)silu(acc[tt][n][4 * g + q]);
+          *reinterpret_cast<bf16x4*>(act + (32 * n + r) * LDA + m0) = hv;
+        }
+      }
+  };
+  auto flush_fallback = [&]() {
+    if (MODE == 1 && p_mask) {
+      const int leader = __ffsll((long long)p_mask) - 1;
+      const int slot = __shfl(p_slot, leader);
+      if (p_unsure) {
         const unsigned rank =
-            __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-        A.fb_ids[slot + rank] = (int32_t)ray;
+            __builtin_amdgcn_mbcnt_hi((unsigned)(p_mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)p_mask, 0u));
+        A.fb_ids[slot + rank] = (int32_t)p_ray;
+      }
+      p_mask = 0;
+    }
+  };
+
+  const int32_t steps = 8 * nb;
+  for (int32_t s = 0; s <= steps; ++s) {
+    const int32_t t = s - grp;
+    const int64_t base = ((int64_t)(blockIdx.x + (int64_t)(t >> 3) * gridDim.x) * 2 + grp) * (4 * RAYS);
+    flush_fallback();
+    if (t >= 0 && t < steps && base < A.m) {
+      const int j = t & 7;
+      if (j == 0) {
+        // input features and layer 0 (K = 4 features as two BF16 terms, padded to 16)
+        const f32x16 bt0 = bias_tile(0, 0), bt1 = bias_tile(0, 1);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          const int64_t ray = base + 32 * n + r;
+          float f[4] = {0.f, 0.f, 0.f, 0.f};
+          if (ray < A.m) {
+            if (MODE == 1) {
+              float al, be;
+              pixel_coords(A.cam, ray, al, be);
+              norm_features(al, be, (float)A.cam.a, (float)A.cam.incl, f);
+            } else {
+              const f32x4 xv = *reinterpret_cast<const f32x4*>(A.x + ray * 4);
+              norm_features(xv[0], xv[1], xv[2], xv[3], f);
+            }
+          }
+          const bf16x8 bx = input_operand(f, half);
+#pragma unroll
+          for (int tt = 0; tt < 2; ++tt) {
+            const bf16x8 aw =
+                *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[0] + wb_index(256, (2 * w + tt) * 32 + r, 8 * half));
+            acc[tt][n] = mfma(aw, bx, tt == 0 ? bt0 : bt1);
+          }
+        }
+        epilogue();
+        prefetch(1);
+      } else if (j == 7) {
+        const int64_t ray = base + 32 * w + r;
+        const bool unsure = output_tile<MODE>(A, act + 32 * w * LDA, ray, r, half);
+        if (MODE == 1) {
+          p_mask = __ballot(unsure);
+          if (p_mask) {
+            const int leader = __ffsll((long long)p_mask) - 1;
+            if (lane == leader) p_slot = atomicAdd(A.fb_count, __popcll(p_mask));
+          }
+          p_unsure = unsure;
+          p_ray = ray;
+        }
+      } else if (j & 1) {
+        // products of hidden layer l = 1..3 over the group's 128 rays; the
+        // first PP_AHEAD k-steps of weights are in flight since the epilogue
+        const int l = (j + 1) >> 1;
+        const __bf16* arow0 = wrow(l, 0);
+        const __bf16* arow1 = wrow(l, 1);
+        bf16x8 bcur[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) bcur[n] = *reinterpret_cast<const bf16x8*>(act + (32 * n + r) * LDA + 8 * half);
+        const f32x16 bt0 = bias_tile(l, 0), bt1 = bias_tile(l, 1);
+#pragma unroll
+        for (int ks = 0; ks < HID / 16; ++ks) {
+          if (ks + PP_AHEAD < HID / 16) {
+            ar[(ks + PP_AHEAD) % (PP_AHEAD + 1)][0] =
+                *reinterpret_cast<const bf16x8*>(arow0 + (ks + PP_AHEAD) * HID * 16);
+            ar[(ks + PP_AHEAD) % (PP_AHEAD + 1)][1] =
+                *reinterpret_cast<const bf16x8*>(arow1 + (ks + PP_AHEAD) * HID * 16);
+          }
+          bf16x8 bnext[4];
+#pragma unroll
+          for (int n = 0; n < 4; ++n)
+            bnext[n] = ks + 1 < HID / 16
+                           ? *reinterpret_cast<const bf16x8*>(act + (32 * n + r) * LDA + (ks + 1) * 16 + 8 * half)
+                           : bcur[n];
+          // keep the scheduler from sinking the loads to their uses
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) {
+            acc[0][n] = mfma(ar[ks % (PP_AHEAD + 1)][0], bcur[n], ks == 0 ? bt0 : acc[0][n]);
+            acc[1][n] = mfma(ar[ks % (PP_AHEAD + 1)][1], bcur[n], ks == 0 ? bt1 : acc[1][n]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) bcur[n] = bnext[n];
+        }
+      } else {
+        epilogue();  // SiLU of layer j / 2 into the group's rows
+        if (j < 6) prefetch((j >> 1) + 1);
       }
     }
+    lds_barrier();
   }
+  flush_fallback();
 }
 
 // Training forward for batches of a few thousand rays: a block of four waves
@@ -333,7 +424,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_train(FwdArgs A) {
 #pragma unroll
         for (int tt = 0; tt < 2; ++tt) {
           const int t = 2 * w + tt;
-          const bf16x8 aw = *reinterpret_cast<const bf16x8*>(wl + (t * 32 + r) * HID + ks * 16 + 8 * half);
+          const bf16x8 aw = *reinterpret_cast<const bf16x8*>(wl + wb_index(HID, t * 32 + r, ks * 16 + 8 * half));
           acc[tt] = mfma(aw, bv, acc[tt]);
         }
       }
@@ -372,7 +463,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_train(FwdArgs A) {
     f32x16 o = zero;
     for (int ks = 0; ks < HID / 16; ++ks) {
       const bf16x8 bv = *reinterpret_cast<const bf16x8*>(in + r * LDA + ks * 16 + 8 * half);
-      const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + r * HID + ks * 16 + 8 * half);
+      const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + wb_index(32, r, ks * 16 + 8 * half));
       o = mfma(aw, bv, o);
     }
     if (half == 0 && valid) {
@@ -530,12 +621,11 @@ __device__ inline void write_bf16(int p, float w, __bf16* wb, __bf16* wbt) {
   const int nw = (l == 0 || l == 4) ? 1024 : 65536;
   if (rel >= nw) return;  // a bias
   const int o = rel / nin, i = rel % nin;
-  const int kpad = l == 0 ? 16 : 256;
   const int offwb = l == 0 ? 0 : l == 1 ? 4096 : l == 2 ? 69632 : l == 3 ? 135168 : 200704;
-  wb[offwb + o * kpad + i] = (__bf16)w;
-  if (l == 0) wb[offwb + o * kpad + 4 + i] = (__bf16)w;  // the lo terms of the split inputs
+  const int mpad = l == 4 ? 32 : 256;
+  wb[offwb + wb_index(mpad, o, i)] = (__bf16)w;
+  if (l == 0) wb[offwb + wb_index(mpad, o, 4 + i)] = (__bf16)w;  // the lo terms of the split inputs
   if (wbt && l >= 1) {
-    const int mpad = l == 4 ? 32 : 256;
     const int offwbt = (l - 1) * 65536;
     wbt[offwbt + i * mpad + o] = (__bf16)w;
   }
@@ -759,6 +849,22 @@ kh_status kh_mlp_sync(kh_ctx* ctx, const kh_mlp* net, void* stream) {
   return KH_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// The persistent inference kernel: one eight-wave block per compute unit (its
+// 132 KB of LDS leaves no room for a second), nb batches of 128 rays per group.
+template <int MODE>
+void launch_fwd(const kh_ctx* ctx, const FwdArgs& A, hipStream_t strm) {
+  const int64_t pairs = (A.m + 8 * RAYS - 1) / (8 * RAYS);
+  const int64_t grid = std::min<int64_t>(std::max(ctx->n_cu, 1), pairs);
+  const int32_t nb = (int32_t)((pairs + grid - 1) / grid);
+  hipLaunchKernelGGL(k_mlp_fwd_pp<MODE>, dim3((unsigned)grid), dim3(8 * 64), 0, strm, A, nb);
+}
+}  // namespace
+
+extern "C" {
+
 kh_status kh_mlp_forward(kh_ctx* ctx, const kh_mlp* net, const float* x, float* y, int64_t m, void* stream) {
   if (!ctx) return KH_EINVAL;
   g_skip_ptr_query = capturing(stream);
@@ -774,8 +880,7 @@ kh_status kh_mlp_forward(kh_ctx* ctx, const kh_mlp* net, const float* x, float* 
   A.x = x;
   A.m = m;
   A.y = y;
-  hipLaunchKernelGGL(k_mlp_fwd_split<0>, dim3((unsigned)((m + 4 * RAYS - 1) / (4 * RAYS))), dim3(256), 0,
-                     (hipStream_t)stream, A);
+  launch_fwd<0>(ctx, A, (hipStream_t)stream);
   KH_HIP(ctx, hipGetLastError());
   return KH_OK;
 }
@@ -881,7 +986,7 @@ kh_status kh_mlp_image(kh_ctx* ctx, const kh_mlp* net, const kh_camera* cam, con
   if (fb->shadow_band > 0.0f && critical_curve(cam->a, cam->incl, &A.crit_ac, A.crit_r)) A.crit_band = fb->shadow_band;
   A.fb_ids = fallback_ids;
   A.fb_count = fallback_count;
-  hipLaunchKernelGGL(k_mlp_fwd_split<1>, dim3((unsigned)((m + 4 * RAYS - 1) / (4 * RAYS))), dim3(256), 0, strm, A);
+  launch_fwd<1>(ctx, A, strm);
   KH_HIP(ctx, hipGetLastError());
   return KH_OK;
 }

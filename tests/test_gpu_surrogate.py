@@ -400,9 +400,10 @@ def test_padding_stays_zero_after_training(ctx):
     """The BF16 copies pad layer 0 to 16 inputs and layer 4 to 32 outputs
     (the matrix-core tile sizes); after Adam steps with nonzero gradients the
     padding is still exactly zero in the forward copy ([256][16] at 0, whose
-    columns 4..7 repeat W0 for the low BF16 terms of the inputs; [32][256] at
-    200,704) and in the transposed copy of layer 4 ([256][32] at 196,608), and
-    the FP32 master weights changed."""
+    columns 4..7 repeat W0 for the low BF16 terms of the inputs; layer 4 at
+    200,704 as 16 k-blocks [16][32][16], element (o, i) at
+    (i // 16) 512 + 16 o + i % 16) and in the transposed copy of layer 4
+    ([256][32] at 196,608), and the FP32 master weights changed."""
     say("mlp padding after training steps")
     p = _random_biases(S.init_params(15), 26)
     net = K.Mlp(p, train=True)
@@ -418,7 +419,7 @@ def test_padding_stays_zero_after_training(ctx):
     wb = net.wb.cpu().numpy()
     wbt = net.wbt.cpu().numpy()
     w0 = wb[:256 * 16].reshape(256, 16)
-    w4 = wb[200704:200704 + 32 * 256].reshape(32, 256)
+    w4 = wb[200704:200704 + 32 * 256].reshape(16, 32, 16).transpose(1, 0, 2).reshape(32, 256)
     w4t = wbt[196608:196608 + 256 * 32].reshape(256, 32)
     assert (w0[:, 8:] == 0).all() and (w0[:, :4] != 0).any()
     assert np.array_equal(w0[:, 4:8], w0[:, :4])
