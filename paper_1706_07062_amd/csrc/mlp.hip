@@ -216,20 +216,43 @@ __device__ inline void lds_barrier() {
 // batch in group g is the 128 rays from 128 (2 (blockIdx + k gridDim) + g).
 // A wave that ends an epilogue requests the first PP_AHEAD k-steps of its next
 // layer's weights, so its products start without waiting for L2; the biases of
-// layers 0..3 sit in LDS and enter as the first k-step's accumulator; the
-// fallback list entry of a tile is written one step after its atomic.
+// layers 0..3 sit in LDS and enter as the first k-step's accumulator; in the
+// output step each wave also computes the input features of its ray tile of
+// the group's next batch (into LDS), and the fallback list entry of a tile is
+// written one step after its atomic.
 constexpr int PP_AHEAD = 2;  // weight k-steps in flight
 template <int MODE>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_mlp_fwd_pp(FwdArgs A, int32_t nb) {
   __shared__ __attribute__((aligned(16))) __bf16 act_all[2 * 4 * RAYS * LDA];
   __shared__ __attribute__((aligned(16))) float bias_s[4 * HID];
+  __shared__ __attribute__((aligned(16))) f32x4 feat_s[2][4 * RAYS];  // features of each group's next batch
   const int tid = threadIdx.x, grp = tid >> 8, w = (tid >> 6) & 3, lane = tid & 63, r = lane & 31, half = lane >> 5;
   __bf16* act = act_all + grp * (4 * RAYS * LDA);
+  auto batch_base = [&](int64_t k) { return ((int64_t)(blockIdx.x + k * gridDim.x) * 2 + grp) * (4 * RAYS); };
+  // the normalised input features of this wave's ray tile of the batch at b0
+  auto features = [&](int64_t b0) {
+    if (half == 0) {
+      const int64_t ray = b0 + 32 * w + r;
+      float f[4] = {0.f, 0.f, 0.f, 0.f};
+      if (ray < A.m) {
+        if (MODE == 1) {
+          float al, be;
+          pixel_coords(A.cam, ray, al, be);
+          norm_features(al, be, (float)A.cam.a, (float)A.cam.incl, f);
+        } else {
+          const f32x4 xv = *reinterpret_cast<const f32x4*>(A.x + ray * 4);
+          norm_features(xv[0], xv[1], xv[2], xv[3], f);
+        }
+      }
+      feat_s[grp][32 * w + r] = f32x4{f[0], f[1], f[2], f[3]};
+    }
+  };
   for (int i = tid; i < 4 * HID; i += 512) {
     const int l = i / HID;
     bias_s[i] = A.params[(l == 0 ? OFF_B[0] : l == 1 ? OFF_B[1] : l == 2 ? OFF_B[2] : OFF_B[3]) + i % HID];
   }
+  features(batch_base(0));
   __syncthreads();
 
   f32x16 acc[2][4];
@@ -292,27 +315,18 @@ k_mlp_fwd_pp(FwdArgs A, int32_t nb) {
   const int32_t steps = 8 * nb;
   for (int32_t s = 0; s <= steps; ++s) {
     const int32_t t = s - grp;
-    const int64_t base = ((int64_t)(blockIdx.x + (int64_t)(t >> 3) * gridDim.x) * 2 + grp) * (4 * RAYS);
+    const int64_t base = batch_base(t >> 3);
     flush_fallback();
     if (t >= 0 && t < steps && base < A.m) {
       const int j = t & 7;
       if (j == 0) {
-        // input features and layer 0 (K = 4 features as two BF16 terms, padded to 16)
+        // layer 0 (K = 4 features as two BF16 terms, padded to 16) on the
+        // features the group's waves left in LDS during the previous step
         const f32x16 bt0 = bias_tile(0, 0), bt1 = bias_tile(0, 1);
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-          const int64_t ray = base + 32 * n + r;
-          float f[4] = {0.f, 0.f, 0.f, 0.f};
-          if (ray < A.m) {
-            if (MODE == 1) {
-              float al, be;
-              pixel_coords(A.cam, ray, al, be);
-              norm_features(al, be, (float)A.cam.a, (float)A.cam.incl, f);
-            } else {
-              const f32x4 xv = *reinterpret_cast<const f32x4*>(A.x + ray * 4);
-              norm_features(xv[0], xv[1], xv[2], xv[3], f);
-            }
-          }
+          const f32x4 fv = feat_s[grp][32 * n + r];
+          const float f[4] = {fv[0], fv[1], fv[2], fv[3]};
           const bf16x8 bx = input_operand(f, half);
 #pragma unroll
           for (int tt = 0; tt < 2; ++tt) {
@@ -326,6 +340,7 @@ k_mlp_fwd_pp(FwdArgs A, int32_t nb) {
       } else if (j == 7) {
         const int64_t ray = base + 32 * w + r;
         const bool unsure = output_tile<MODE>(A, act + 32 * w * LDA, ray, r, half);
+        features(batch_base((t >> 3) + 1));
         if (MODE == 1) {
           p_mask = __ballot(unsure);
           if (p_mask) {
