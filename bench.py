@@ -612,7 +612,7 @@ def surrogate_image_only():
     sur = SU.Surrogate(ctx, seed=0)
     cam = W.surrogate_eval_camera()
     ms = []
-    for _ in range(3):
+    for _ in range(8):  # the clocks settle over the first few launches
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         _, _, cnt = sur.image(cam, 0.2)
@@ -640,7 +640,7 @@ def main():
     ap.add_argument("--elapse-only", action="store_true",
                     help="only the fixed-step chart / layout comparison (Sec. 4's tab:elapse), for profilers")
     ap.add_argument("--surrogate-image-only", action="store_true",
-                    help="only the network's 4096^2 image, three times, with untrained seed-0 weights (for profilers)")
+                    help="only the network's 4096^2 image, eight times, with untrained seed-0 weights (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the integrator shards by ray range with no exchange on the hot "
