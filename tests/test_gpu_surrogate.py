@@ -396,6 +396,37 @@ def test_forward_single_ray_and_one_past_a_block(ctx):
         assert torch.equal(y, full[:m])
 
 
+def test_forward_persistent_batches_and_tail(ctx):
+    """The inference kernel is persistent (one block per compute unit, several
+    128-ray batches per wave group): 197,385 rays (four batches per group on
+    256 compute units, the last ones partly or wholly past the end) match the
+    reference on a strided sample, leave the memory past y[m] untouched, and
+    every ray's output is bitwise the one it gets in a short call of its own
+    slice, wherever the slice falls in the long call's batches."""
+    say("mlp forward: persistent batches and tail")
+    p = _random_biases(S.init_params(17), 27)
+    net = K.Mlp(p, train=False)
+    ctx.kh_mlp_sync(net)
+    m = 3 * 65536 + 777
+    g = np.random.default_rng(1706070627)
+    x = np.stack([g.uniform(-12, 12, m), g.uniform(-12, 12, m), g.uniform(0, 0.998, m),
+                  np.radians(g.uniform(5, 85, m))], axis=1).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    y = torch.full((m + 64, 4), float("nan"), dtype=torch.float32, device="cuda")
+    ctx.kh_mlp_forward(net, xd, y[:m])
+    got = y.cpu().numpy()
+    assert np.isnan(got[m:]).all()
+    idx = np.arange(0, m, 97)
+    want, _ = M.forward(p.astype(np.float64), x[idx].astype(np.float64), bf16_storage=True)
+    err = np.abs(got[idx] - want).max() / np.abs(want).max()
+    say(f"  sampled max abs err / max |y| = {err:.2e}")
+    assert err < 2e-3
+    for start, n in ((0, 129), (65536 - 50, 300), (131072 + 7, 1000), (m - 300, 300)):
+        part = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        ctx.kh_mlp_forward(net, xd[start:start + n].contiguous(), part)
+        assert np.array_equal(part.cpu().numpy(), got[start:start + n]), (start, n)
+
+
 def test_padding_stays_zero_after_training(ctx):
     """The BF16 copies pad layer 0 to 16 inputs and layer 4 to 32 outputs
     (the matrix-core tile sizes); after Adam steps with nonzero gradients the
