@@ -250,6 +250,10 @@ void lower(double a, const double x[4], const double k[4], double kl[4]) {
 // spheroidal angle of the Kerr-Schild chart: cos(theta) = z / r,
 // sin(theta) = rho / sqrt(r^2 + a^2), rho = sqrt(x^2 + y^2), and
 // p_theta = k_i dx^i/dtheta = cot(theta) (x k_x + y k_y) - r sin(theta) k_z.
+// On the spin axis (rho = 0, where both quotients are 0/0) Q takes its limit:
+// p_theta^2 + cos^2(theta) L_z^2 / sin^2(theta) tends to
+// cos^2(theta) (r^2 + a^2) (k_x^2 + k_y^2) from every direction, and there
+// the covariant k_x, k_y equal the contravariant ones.
 void constants(double a, const double x[4], const double k[4], double out[4]) {
   double kl[4];
   lower(a, x, k, kl);
@@ -262,11 +266,15 @@ void constants(double a, const double x[4], const double k[4], double out[4]) {
   double Lz = x[1] * kl[2] - x[2] * kl[1];
   double r = radius(a, x);
   double rho = std::sqrt(x[1] * x[1] + x[2] * x[2]);
-  if (rho < 1e-300) rho = 1e-300;
   double cth = x[3] / r;
-  double sth = rho / std::sqrt(r * r + a * a);
-  double pth = (cth / sth) * (x[1] * kl[1] + x[2] * kl[2]) - r * sth * kl[3];
-  double Q = pth * pth + cth * cth * (a * a * (mu2 - E * E) + Lz * Lz / (sth * sth));
+  double Q;
+  if (rho > 1e-150) {
+    double sth = rho / std::sqrt(r * r + a * a);
+    double pth = (cth / sth) * (x[1] * kl[1] + x[2] * kl[2]) - r * sth * kl[3];
+    Q = pth * pth + cth * cth * (a * a * (mu2 - E * E) + Lz * Lz / (sth * sth));
+  } else {
+    Q = cth * cth * ((r * r + a * a) * (kl[1] * kl[1] + kl[2] * kl[2]) + a * a * (mu2 - E * E));
+  }
   out[0] = E;
   out[1] = Lz;
   out[2] = Q;
@@ -1220,7 +1228,9 @@ void deriv_bl(double a, const double y[8], double dy[8]) {
 }
 
 // E = -k_t, L_z = k_phi, mu^2 = -g k k and Carter's constant
-// Q = k_theta^2 + cos^2(theta) [a^2 (mu^2 - E^2) + L_z^2 / sin^2(theta)].
+// Q = k_theta^2 + cos^2(theta) [a^2 (mu^2 - E^2) + L_z^2 / sin^2(theta)].  On the
+// axis (sin(theta) = 0), where the chart is singular, L_z = 0 and the last
+// term is taken as its limit 0.
 void bl_constants(double a, const double x[4], const double k[4], double out[4]) {
   double g[4][4];
   bl_metric(a, x[1], x[2], g);
@@ -1234,7 +1244,7 @@ void bl_constants(double a, const double x[4], const double k[4], double out[4])
   double c = std::cos(x[2]), s = std::sin(x[2]);
   out[0] = E;
   out[1] = Lz;
-  out[2] = kl[2] * kl[2] + c * c * (a * a * (mu2 - E * E) + Lz * Lz / (s * s));
+  out[2] = kl[2] * kl[2] + c * c * (a * a * (mu2 - E * E) + (Lz == 0.0 ? 0.0 : Lz * Lz / (s * s)));
   out[3] = mu2;
 }
 

@@ -328,7 +328,10 @@ __host__ __device__ inline double timelike_u0(double a, const double x[4], const
 // mu^2 = -g k k, with covariant k_a = eta_ab k^b + f l_a (l.k).  Q uses the
 // spheroidal angle of the chart: cos(th) = z/r, sin(th) = rho / sqrt(r^2 + a^2),
 // p_th = cot(th)(x k_x + y k_y) - r sin(th) k_z,
-// Q = p_th^2 + cos^2(th) [a^2 (mu^2 - E^2) + L_z^2 / sin^2(th)].
+// Q = p_th^2 + cos^2(th) [a^2 (mu^2 - E^2) + L_z^2 / sin^2(th)].  On the spin
+// axis (rho = 0) the two quotients are 0/0 and Q is their limit,
+// cos^2(th) [(r^2 + a^2)(k_x^2 + k_y^2) + a^2 (mu^2 - E^2)], the same from
+// every direction.
 __host__ __device__ inline void constants(double a, const double x[4], const double k[4], double out[4]) {
   const double a2 = a * a;
   const double r2 = ks_r2(a2, x[1], x[2], x[3]);
@@ -341,14 +344,17 @@ __host__ __device__ inline void constants(double a, const double x[4], const dou
   const double E = -k0;
   const double Lz = x[1] * ky - x[2] * kx;
   const double mu2 = -(k0 * k[0] + kx * k[1] + ky * k[2] + kz * k[3]);
-  double rho = sqrt(x[1] * x[1] + x[2] * x[2]);
-  rho = rho < 1e-300 ? 1e-300 : rho;
+  const double rho = sqrt(x[1] * x[1] + x[2] * x[2]);
   const double cth = x[3] / r;
-  const double sth = rho * sqrt(iS);
-  const double pth = (cth / sth) * (x[1] * kx + x[2] * ky) - r * sth * kz;
   out[0] = E;
   out[1] = Lz;
-  out[2] = pth * pth + cth * cth * (a2 * (mu2 - E * E) + Lz * Lz / (sth * sth));
+  if (rho > 1e-150) {
+    const double sth = rho * sqrt(iS);
+    const double pth = (cth / sth) * (x[1] * kx + x[2] * ky) - r * sth * kz;
+    out[2] = pth * pth + cth * cth * (a2 * (mu2 - E * E) + Lz * Lz / (sth * sth));
+  } else {
+    out[2] = cth * cth * ((r2 + a2) * (kx * kx + ky * ky) + a2 * (mu2 - E * E));
+  }
   out[3] = mu2;
 }
 

@@ -126,10 +126,18 @@ def test_rk4_step_matches_oracle(H):
 
 def test_constants_and_redshift_match_oracle(H):
     for a in (0.0, 0.6, -0.99):
-        for y in _states(20, a):
+        # random states, and states on the spin axis (where Q is a limit)
+        axis = [np.array([0.0, 0.0, 0.0, z, 0.0, *rng.normal(size=3)]) for z in (2.5, -7.0, 40.0)]
+        for y in _states(20, a) + axis:
+            if y[1] == 0.0 and y[2] == 0.0:
+                g, _ = O.metric(a, y[:4])
+                k = y[5:]
+                A, B, Cq = g[0, 0], g[0, 1:] @ k, k @ g[1:, 1:] @ k
+                y[4] = (B + np.sqrt(B * B - A * Cq)) / (-A)
             out = np.zeros(4)
             H.host_constants(a, _p(y[:4].copy()), _p(y[4:].copy()), _p(out))
             want = O.constants(a, y[:4], y[4:])
+            assert np.all(np.isfinite(out)) and np.all(np.isfinite(want))
             np.testing.assert_allclose(out, want, rtol=1e-11, atol=1e-11 * np.abs(want).max())
     for r, xi, a in [(6.0, 2.0, 0.0), (2.0, -3.0, 0.99), (30.0, 5.0, 0.5), (1.2, 1.0, 0.9)]:
         g1, g2 = H.host_redshift(r, xi, a), O.redshift(r, xi, a)
