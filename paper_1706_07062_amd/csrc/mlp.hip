@@ -54,7 +54,8 @@ constexpr int OUT_DIM[5] = {256, 256, 256, 256, 4};
 constexpr int KPAD[5] = {16, 256, 256, 256, 256};
 constexpr int MPAD[5] = {256, 256, 256, 256, 32};
 constexpr int OFF_WB[5] = {0, 4096, 69632, 135168, 200704};
-// BF16 transposed copies of layers 1..4: [KPAD_l][MPAD_l].
+// BF16 transposed copies W^T of layers 1..4 (rows: the 256 inputs; k: the
+// padded outputs) in 16-output k-blocks: element (i, o) at wb_index(256, i, o).
 constexpr int OFF_WBT[5] = {0, 0, 65536, 131072, 196608};
 
 // Element (o, i) of the forward copy of a layer with mpad padded rows: the
@@ -401,7 +402,7 @@ k_mlp_fwd_pp(FwdArgs A, int32_t nb) {
 // busy instead of b / 32.  The tile's activations live in LDS ([ray][feature]
 // rows, double-buffered: one barrier per layer).  Saves what the backward
 // pass needs: pre-activations z and the transposed BF16 activations.
-__global__ void __launch_bounds__(256) k_mlp_fwd_train(FwdArgs A) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_mlp_fwd_train(FwdArgs A) {
   __shared__ __attribute__((aligned(16))) __bf16 act[2][RAYS * LDA];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = lane & 31, half = lane >> 5;
   const int64_t ray = (int64_t)blockIdx.x * RAYS + r;
@@ -434,14 +435,20 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_train(FwdArgs A) {
       const __bf16* wl = A.wb + (l == 1 ? OFF_WB[1] : l == 2 ? OFF_WB[2] : OFF_WB[3]);
 #pragma unroll
       for (int tt = 0; tt < 2; ++tt) acc[tt] = zero;
+      // a batch keeps one wave per SIMD busy, so nothing hides a load's
+      // latency: all 32 weight fragments of the layer are requested first
+      bf16x8 aw[HID / 16][2];
+#pragma unroll
+      for (int ks = 0; ks < HID / 16; ++ks)
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt)
+          aw[ks][tt] = *reinterpret_cast<const bf16x8*>(wl + wb_index(HID, (2 * w + tt) * 32 + r, ks * 16 + 8 * half));
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
       for (int ks = 0; ks < HID / 16; ++ks) {
         const bf16x8 bv = *reinterpret_cast<const bf16x8*>(in + r * LDA + ks * 16 + 8 * half);
 #pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
-          const int t = 2 * w + tt;
-          const bf16x8 aw = *reinterpret_cast<const bf16x8*>(wl + wb_index(HID, t * 32 + r, ks * 16 + 8 * half));
-          acc[tt] = mfma(aw, bv, acc[tt]);
-        }
+        for (int tt = 0; tt < 2; ++tt) acc[tt] = mfma(aw[ks][tt], bv, acc[tt]);
       }
     }
     // bias, SiLU, the next activation rows and the saved tensors of this wave's outputs
@@ -476,10 +483,15 @@ __global__ void __launch_bounds__(256) k_mlp_fwd_train(FwdArgs A) {
   if (w == 0) {
     const __bf16* in = act[1];
     f32x16 o = zero;
+    bf16x8 aw[HID / 16];
+#pragma unroll
+    for (int ks = 0; ks < HID / 16; ++ks)
+      aw[ks] = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + wb_index(32, r, ks * 16 + 8 * half));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
     for (int ks = 0; ks < HID / 16; ++ks) {
       const bf16x8 bv = *reinterpret_cast<const bf16x8*>(in + r * LDA + ks * 16 + 8 * half);
-      const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + wb_index(32, r, ks * 16 + 8 * half));
-      o = mfma(aw, bv, o);
+      o = mfma(aw[ks], bv, o);
     }
     if (half == 0 && valid) {
       const float* b4 = A.params + OFF_B[4];
@@ -530,25 +542,30 @@ __global__ void k_mlp_loss(const float* y, const float* t, const uint8_t* mask, 
 
 // Gradient with respect to a layer's input, times SiLU' of the layer below:
 // dz_out[ray][k] = (sum_o dz[ray][o] W[o][k]) * silu'(zprev[ray][k]).
-__global__ void __launch_bounds__(256) k_mlp_bwd_dx(const __bf16* wbt, int opad, const __bf16* dz, const float* zprev,
-                                                     __bf16* dz_out, __bf16* dzT_out, int64_t bmax) {
-  // one tile of 32 rays per block; wave w computes input features 64 w .. 64 w + 63
+template <int OPAD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_mlp_bwd_dx(const __bf16* wbt, const __bf16* dz, const float* zprev, __bf16* dz_out, __bf16* dzT_out, int64_t bmax) {
+  // one tile of 32 rays per block; wave w computes input features 64 w .. 64 w + 63;
+  // every fragment is requested before the first product (one wave per SIMD)
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = lane & 31, half = lane >> 5;
   const int64_t ray = (int64_t)blockIdx.x * RAYS + r;
   f32x16 acc[2];
   const f32x16 zero = {};
 #pragma unroll
   for (int tt = 0; tt < 2; ++tt) acc[tt] = zero;
-#pragma unroll 4
-  for (int os = 0; os < opad / 16; ++os) {
-    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(dz + ray * opad + os * 16 + 8 * half);
+  bf16x8 aw[OPAD / 16][2], bv[OPAD / 16];
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-      const int t = 2 * w + tt;
-      const bf16x8 aw = *reinterpret_cast<const bf16x8*>(wbt + (t * 32 + r) * opad + os * 16 + 8 * half);
-      acc[tt] = mfma(aw, bv, acc[tt]);
-    }
+  for (int os = 0; os < OPAD / 16; ++os) {
+    bv[os] = *reinterpret_cast<const bf16x8*>(dz + ray * OPAD + os * 16 + 8 * half);
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+      aw[os][tt] = *reinterpret_cast<const bf16x8*>(wbt + wb_index(HID, (2 * w + tt) * 32 + r, os * 16 + 8 * half));
   }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int os = 0; os < OPAD / 16; ++os)
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) acc[tt] = mfma(aw[os][tt], bv[os], acc[tt]);
 #pragma unroll
   for (int tt = 0; tt < 2; ++tt) {
 #pragma unroll
@@ -568,7 +585,7 @@ __global__ void __launch_bounds__(256) k_mlp_bwd_dx(const __bf16* wbt, int opad,
 // Split-batch partial weight and bias gradients of one layer:
 // part[s][W_l + o * nin + i] = sum over split s of dz[b][o] h[b][i],
 // part[s][b_l + o] = sum over split s of dz[b][o].
-__global__ void __launch_bounds__(64) k_mlp_bwd_dw(const __bf16* dzT, int opad, int nout, const __bf16* ht, int ipad,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) k_mlp_bwd_dw(const __bf16* dzT, int opad, int nout, const __bf16* ht, int ipad,
                                                     int nin, int64_t bmax, int64_t b, float* part, int off_w,
                                                     int off_b) {
   const int lane = threadIdx.x, r = lane & 31, half = lane >> 5;
@@ -586,17 +603,18 @@ __global__ void __launch_bounds__(64) k_mlp_bwd_dw(const __bf16* dzT, int opad, 
   const __bf16* arow = dzT + (int64_t)(ot * 32 + r) * bmax + 8 * half;
   const __bf16* brow = ht + (int64_t)(it * 32 + r) * bmax + 8 * half;
   int64_t kb = b0;
-  // eight k-steps' fragments are loaded before their products, so eight L2
-  // round trips overlap; the accumulation order is unchanged
-  for (; kb + 128 <= b1; kb += 128) {
-    bf16x8 aw[8], bv[8];
+  // sixteen k-steps' fragments are loaded before their products, so sixteen
+  // L2 round trips overlap; the accumulation order is unchanged
+  for (; kb + 256 <= b1; kb += 256) {
+    bf16x8 aw[16], bv[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       aw[u] = *reinterpret_cast<const bf16x8*>(arow + kb + 16 * u);
       bv[u] = *reinterpret_cast<const bf16x8*>(brow + kb + 16 * u);
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc = mfma(aw[u], bv[u], acc);
+    for (int u = 0; u < 16; ++u) acc = mfma(aw[u], bv[u], acc);
   }
   for (; kb < b1; kb += 16) acc = mfma(*reinterpret_cast<const bf16x8*>(arow + kb), *reinterpret_cast<const bf16x8*>(brow + kb), acc);
   float* ps = part + (int64_t)s * NP;
@@ -613,8 +631,19 @@ __global__ void __launch_bounds__(64) k_mlp_bwd_dw(const __bf16* dzT, int opad, 
     const int64_t mid = b0 + per / 2;
     const __bf16* row = dzT + (int64_t)o * bmax;
     float sb = 0.0f;
-#pragma unroll 4
-    for (int64_t kb = half ? mid : b0; kb < (half ? b1 : mid); kb += 8) {
+    int64_t kb = half ? mid : b0;
+    const int64_t ke = half ? b1 : mid;
+    for (; kb + 128 <= ke; kb += 128) {
+      bf16x8 v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = *reinterpret_cast<const bf16x8*>(row + kb + 8 * u);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sb += (float)v[u][j];
+    }
+    for (; kb < ke; kb += 8) {
       const bf16x8 v = *reinterpret_cast<const bf16x8*>(row + kb);
 #pragma unroll
       for (int j = 0; j < 8; ++j) sb += (float)v[j];
@@ -641,8 +670,10 @@ __device__ inline void write_bf16(int p, float w, __bf16* wb, __bf16* wbt) {
   wb[offwb + wb_index(mpad, o, i)] = (__bf16)w;
   if (l == 0) wb[offwb + wb_index(mpad, o, 4 + i)] = (__bf16)w;  // the lo terms of the split inputs
   if (wbt && l >= 1) {
+    // W^T of the layer: rows are the 256 inputs, k the (padded) outputs,
+    // stored in 16-output k-blocks [256][16]
     const int offwbt = (l - 1) * 65536;
-    wbt[offwbt + i * mpad + o] = (__bf16)w;
+    wbt[offwbt + wb_index(HID, i, o)] = (__bf16)w;
   }
 }
 
@@ -812,7 +843,7 @@ kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batc
   // layer 4
   hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(1 * 8 * SPLITS), dim3(64), 0, strm, w.dz4T, 32, 4, ht(4), 256, 256, bmax,
                      (int64_t)b, w.part, h_OFF_W[4], h_OFF_B[4]);
-  hipLaunchKernelGGL(k_mlp_bwd_dx, gdx, dim3(256), 0, strm, wbt + OFF_WBT[4], 32, w.dz4, zl(3), w.dz_a, w.dzT_a, bmax);
+  hipLaunchKernelGGL(k_mlp_bwd_dx<32>, gdx, dim3(256), 0, strm, wbt + OFF_WBT[4], w.dz4, zl(3), w.dz_a, w.dzT_a, bmax);
   // layers 3, 2, 1
   __bf16* cur = w.dz_a;
   __bf16* curT = w.dzT_a;
@@ -821,7 +852,7 @@ kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batc
   for (int l = 3; l >= 1; --l) {
     hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(8 * 8 * SPLITS), dim3(64), 0, strm, curT, 256, 256, ht(l), 256, 256, bmax,
                        (int64_t)b, w.part, h_OFF_W[l], h_OFF_B[l]);
-    hipLaunchKernelGGL(k_mlp_bwd_dx, gdx, dim3(256), 0, strm, wbt + OFF_WBT[l], 256, cur, zl(l - 1), nxt, nxtT, bmax);
+    hipLaunchKernelGGL(k_mlp_bwd_dx<256>, gdx, dim3(256), 0, strm, wbt + OFF_WBT[l], cur, zl(l - 1), nxt, nxtT, bmax);
     std::swap(cur, nxt);
     std::swap(curT, nxtT);
   }

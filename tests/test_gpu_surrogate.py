@@ -434,7 +434,8 @@ def test_padding_stays_zero_after_training(ctx):
     columns 4..7 repeat W0 for the low BF16 terms of the inputs; layer 4 at
     200,704 as 16 k-blocks [16][32][16], element (o, i) at
     (i // 16) 512 + 16 o + i % 16) and in the transposed copy of layer 4
-    ([256][32] at 196,608), and the FP32 master weights changed."""
+    (at 196,608 as 2 k-blocks [2][256][16], element (i, o) at
+    (o // 16) 4096 + 16 i + o % 16), and the FP32 master weights changed."""
     say("mlp padding after training steps")
     p = _random_biases(S.init_params(15), 26)
     net = K.Mlp(p, train=True)
@@ -451,7 +452,7 @@ def test_padding_stays_zero_after_training(ctx):
     wbt = net.wbt.cpu().numpy()
     w0 = wb[:256 * 16].reshape(256, 16)
     w4 = wb[200704:200704 + 32 * 256].reshape(16, 32, 16).transpose(1, 0, 2).reshape(32, 256)
-    w4t = wbt[196608:196608 + 256 * 32].reshape(256, 32)
+    w4t = wbt[196608:196608 + 256 * 32].reshape(2, 256, 16).transpose(1, 0, 2).reshape(256, 32)
     assert (w0[:, 8:] == 0).all() and (w0[:, :4] != 0).any()
     assert np.array_equal(w0[:, 4:8], w0[:, :4])
     assert (w4[4:] == 0).all() and (w4[:4] != 0).any()
