@@ -9,7 +9,7 @@
 // the next activation row are one 8-byte write.  In every kernel the waves of
 // a block split each layer's 256 outputs and share the block's activations in
 // LDS rows [ray][feature]: inference (k_mlp_fwd_pp) with 128 rays per group
-// of four waves, training (k_mlp_fwd_train, k_mlp_bwd_dx) with 32, because a
+// of four waves, training (k_mlp_fwd_train, k_mlp_bwd) with 32, because a
 // training batch is only a few thousand rays.
 //
 // MFMA operand layout used (v_mfma_f32_32x32x16_bf16, 64 lanes):
@@ -542,13 +542,39 @@ __global__ void k_mlp_loss(const float* y, const float* t, const uint8_t* mask, 
 
 // Gradient with respect to a layer's input, times SiLU' of the layer below:
 // dz_out[ray][k] = (sum_o dz[ray][o] W[o][k]) * silu'(zprev[ray][k]).
+// Arguments of one layer's backward launch (k_mlp_bwd): its weight-gradient
+// tasks and, except for layer 0, its input-gradient ray tiles.
+struct BwdLayer {
+  // weight and bias gradient: dz^T [opad][bmax] (BF16), h^T [ipad][bmax]
+  const __bf16* dzT;
+  int opad, nout;
+  const __bf16* ht;
+  int ipad, nin, tiles;  // tiles = (opad / 32) (ipad / 32)
+  int64_t bmax, b;
+  float* part;
+  int off_w, off_b;
+  // input gradient: W^T (k-blocks), dz [bmax][opad], the layer below's z
+  const __bf16* wbt;
+  const __bf16* dz;
+  const float* zprev;
+  __bf16* dz_out;
+  __bf16* dzT_out;
+  int ndx;  // ray tiles (blocks) of the input gradient, a multiple of 8
+};
+
+// Gradient with respect to a layer's input for ray tile `blk` (one 32-ray
+// tile per block; wave w computes input features 64 w .. 64 w + 63); every
+// fragment is requested before the first product (one wave per SIMD).
 template <int OPAD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_mlp_bwd_dx(const __bf16* wbt, const __bf16* dz, const float* zprev, __bf16* dz_out, __bf16* dzT_out, int64_t bmax) {
-  // one tile of 32 rays per block; wave w computes input features 64 w .. 64 w + 63;
-  // every fragment is requested before the first product (one wave per SIMD)
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = lane & 31, half = lane >> 5;
-  const int64_t ray = (int64_t)blockIdx.x * RAYS + r;
+__device__ inline void bwd_dx_tile(const BwdLayer& L, int blk, int w, int lane) {
+  const __bf16* wbt = L.wbt;
+  const __bf16* dz = L.dz;
+  const float* zprev = L.zprev;
+  __bf16* dz_out = L.dz_out;
+  __bf16* dzT_out = L.dzT_out;
+  const int64_t bmax = L.bmax;
+  const int r = lane & 31, half = lane >> 5;
+  const int64_t ray = (int64_t)blk * RAYS + r;
   f32x16 acc[2];
   const f32x16 zero = {};
 #pragma unroll
@@ -585,15 +611,18 @@ k_mlp_bwd_dx(const __bf16* wbt, const __bf16* dz, const float* zprev, __bf16* dz
 // Split-batch partial weight and bias gradients of one layer:
 // part[s][W_l + o * nin + i] = sum over split s of dz[b][o] h[b][i],
 // part[s][b_l + o] = sum over split s of dz[b][o].
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) k_mlp_bwd_dw(const __bf16* dzT, int opad, int nout, const __bf16* ht, int ipad,
-                                                    int nin, int64_t bmax, int64_t b, float* part, int off_w,
-                                                    int off_b) {
-  const int lane = threadIdx.x, r = lane & 31, half = lane >> 5;
-  const int tiles_i = ipad / 32, tiles = gridDim.x / SPLITS;
-  // Workgroups go to the 8 XCDs round-robin by linear id; give each XCD two
-  // whole batch splits (all output tiles of them), so that an XCD's L2 holds
-  // only its 1/8 of dz^T and h instead of every tile's re-read of all of it.
-  const int xcd = blockIdx.x % 8, j = blockIdx.x / 8;
+// Task j (0 .. 2 tiles - 1) of XCD xcd: workgroups go to the 8 XCDs
+// round-robin by linear id, and each XCD takes two whole batch splits (all
+// output tiles of them), so that an XCD's L2 holds only its 1/8 of dz^T and h
+// instead of every tile's re-read of all of it.
+__device__ inline void bwd_dw_task(const BwdLayer& L, int xcd, int j, int lane) {
+  const __bf16* dzT = L.dzT;
+  const __bf16* ht = L.ht;
+  const int nout = L.nout, ipad = L.ipad, nin = L.nin, tiles = L.tiles, off_w = L.off_w, off_b = L.off_b;
+  const int64_t bmax = L.bmax, b = L.b;
+  float* part = L.part;
+  const int r = lane & 31, half = lane >> 5;
+  const int tiles_i = ipad / 32;
   const int s = xcd * (SPLITS / 8) + j / tiles;
   const int tile = j % tiles;
   const int ot = tile / tiles_i, it = tile % tiles_i;
@@ -651,6 +680,23 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
     sb += __shfl_down(sb, 32);
     if (half == 0 && o < nout) ps[off_b + o] = sb;
   }
+}
+
+// One layer's backward pass in one launch: blocks 0 .. ndx - 1 compute the
+// input gradient of a ray tile each, the rest four weight-gradient tasks each
+// (the two parts are independent, so their latencies overlap).
+template <int OPAD, bool DX>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_mlp_bwd(BwdLayer L) {
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  int blk = blockIdx.x;
+  if (DX) {
+    if (blk < L.ndx) {
+      bwd_dx_tile<OPAD>(L, blk, w, lane);
+      return;
+    }
+    blk -= L.ndx;  // ndx is a multiple of 8: blk % 8 is still the block's XCD
+  }
+  bwd_dw_task(L, blk % 8, (blk / 8) * 4 + w, lane);
 }
 
 __device__ inline int layer_of(int p) {
@@ -839,26 +885,50 @@ kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batc
   const __bf16* wbt = reinterpret_cast<const __bf16*>(net->wbt);
   auto ht = [&](int l) { return ht_layer(w.ht, l, bmax); };
   auto zl = [&](int l) { return w.z + (int64_t)l * bmax * HID; };
-  const dim3 gdx((unsigned)(b / RAYS));
-  // layer 4
-  hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(1 * 8 * SPLITS), dim3(64), 0, strm, w.dz4T, 32, 4, ht(4), 256, 256, bmax,
-                     (int64_t)b, w.part, h_OFF_W[4], h_OFF_B[4]);
-  hipLaunchKernelGGL(k_mlp_bwd_dx<32>, gdx, dim3(256), 0, strm, wbt + OFF_WBT[4], w.dz4, zl(3), w.dz_a, w.dzT_a, bmax);
-  // layers 3, 2, 1
+  const int ndx = (int)(b / RAYS);
+  // one launch per layer: the layer's weight gradient (split over the batch,
+  // 4 tiles per block) beside the gradient of its input
+  auto layer = [&](int l, const __bf16* dzT, const __bf16* dz, __bf16* dz_out, __bf16* dzT_out) {
+    BwdLayer L{};
+    L.dzT = dzT;
+    L.opad = l == 4 ? 32 : 256;
+    L.nout = l == 4 ? 4 : 256;
+    L.ht = ht(l);
+    L.ipad = l == 0 ? 32 : 256;
+    L.nin = l == 0 ? 4 : 256;
+    L.tiles = (L.opad / 32) * (L.ipad / 32);
+    L.bmax = bmax;
+    L.b = b;
+    L.part = w.part;
+    L.off_w = h_OFF_W[l];
+    L.off_b = h_OFF_B[l];
+    L.ndx = l == 0 ? 0 : ndx;
+    if (l > 0) {
+      L.wbt = wbt + OFF_WBT[l];
+      L.dz = dz;
+      L.zprev = zl(l - 1);
+      L.dz_out = dz_out;
+      L.dzT_out = dzT_out;
+    }
+    const dim3 grid((unsigned)(L.ndx + 4 * L.tiles));
+    if (l == 4)
+      hipLaunchKernelGGL((k_mlp_bwd<32, true>), grid, dim3(256), 0, strm, L);
+    else if (l > 0)
+      hipLaunchKernelGGL((k_mlp_bwd<256, true>), grid, dim3(256), 0, strm, L);
+    else
+      hipLaunchKernelGGL((k_mlp_bwd<256, false>), grid, dim3(256), 0, strm, L);
+  };
+  layer(4, w.dz4T, w.dz4, w.dz_a, w.dzT_a);
   __bf16* cur = w.dz_a;
   __bf16* curT = w.dzT_a;
   __bf16* nxt = w.dz_b;
   __bf16* nxtT = w.dzT_b;
   for (int l = 3; l >= 1; --l) {
-    hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(8 * 8 * SPLITS), dim3(64), 0, strm, curT, 256, 256, ht(l), 256, 256, bmax,
-                       (int64_t)b, w.part, h_OFF_W[l], h_OFF_B[l]);
-    hipLaunchKernelGGL(k_mlp_bwd_dx<256>, gdx, dim3(256), 0, strm, wbt + OFF_WBT[l], cur, zl(l - 1), nxt, nxtT, bmax);
+    layer(l, curT, cur, nxt, nxtT);
     std::swap(cur, nxt);
     std::swap(curT, nxtT);
   }
-  // layer 0 (inputs padded to one 32-row tile)
-  hipLaunchKernelGGL(k_mlp_bwd_dw, dim3(8 * 1 * SPLITS), dim3(64), 0, strm, curT, 256, 256, ht(0), 32, 4, bmax,
-                     (int64_t)b, w.part, h_OFF_W[0], h_OFF_B[0]);
+  layer(0, curT, nullptr, nullptr, nullptr);  // inputs padded to one 32-row tile
   KH_HIP(ctx, hipGetLastError());
   return KH_OK;
 }
