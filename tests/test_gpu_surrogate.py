@@ -115,17 +115,19 @@ def test_gradient_matches_reference(ctx):
             off += size
 
 
-def test_image_kernel_decodes_forward_and_lists_fallback(ctx):
-    """The camera-image kernel on a ragged 37x23 camera (6 full blocks of 128
-    rays + 83): its decoded outputs equal the forward kernel's raw outputs,
-    decoded on the host, on the same pixel features; they match the FP64
-    reference with BF16 storage; and the fallback list is exactly the set of
-    pixels whose capture probability lies in (tau, 1 - tau), in any order."""
-    say("mlp image kernel")
+@pytest.mark.parametrize("wh", [(37, 23), (1, 1), (300, 1), (1, 257)])
+def test_image_kernel_decodes_forward_and_lists_fallback(ctx, wh):
+    """The camera-image kernel on ragged cameras (37x23: 6 full 128-ray
+    batches + 83; a single pixel; one row; one column): its decoded outputs
+    equal the forward kernel's raw outputs, decoded on the host, on the same
+    pixel features; they match the FP64 reference with BF16 storage; and the
+    fallback list is exactly the set of pixels whose capture probability lies
+    in (tau, 1 - tau), in any order."""
+    say(f"mlp image kernel {wh[0]}x{wh[1]}")
     p = _random_biases(S.init_params(12), 22)
     net = K.Mlp(p, train=False)
     ctx.kh_mlp_sync(net)
-    cam = W.Camera(0.9, 1000.0, 45.0, -12.0, 12.0, -9.0, 9.0, 37, 23)
+    cam = W.Camera(0.9, 1000.0, 45.0, -12.0, 12.0, -9.0, 9.0, *wh)
     n = cam.n
     col, row = np.arange(n) % cam.width, np.arange(n) // cam.width
     al = cam.alpha_min + (col + 0.5) * (cam.alpha_max - cam.alpha_min) / cam.width
