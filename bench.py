@@ -524,7 +524,7 @@ def cpu_baseline(args):
 
     cores = O.default_threads()
     outs = []
-    done, t_total = 0, 0.0
+    done, t_total, attempts = 0, 0.0, 0
     cams = W.kerr_1024()
     for j, (cam, ids) in enumerate(zip(cams, headline_sample_ids(args.cpu_sample))):
         pix = ids - j * cam.n
@@ -534,6 +534,7 @@ def cpu_baseline(args):
         outs.append(O.integrate(init, O.Params(method=O.DOPRI5, k_cross=4), nthreads=cores))
         t_total += time.perf_counter() - t0
         done += len(pix)
+        attempts += int(outs[-1]["n_acc"].sum()) + int(outs[-1]["n_rej"].sum())
     log(f"cpu oracle: {done} rays in {t_total:.2f} s on {cores} threads")
     ref = {k: np.concatenate([o[k] for o in outs], axis=-1 if k == "s" else 0) for k in ("s", "status", "n_cross",
                                                                                         "cross")}
@@ -559,9 +560,20 @@ def cpu_baseline(args):
         gb = dict(s=g["s"], status=g["status"])
         errors["batched_mixed"] = result_errors(gb, o)
         log(f"error vs oracle, batched_mixed: {errors['batched_mixed']}")
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    # a DOPRI5 attempt evaluates six right-hand sides, plus one first stage per ray
+    rhs = 6 * attempts + done
     return dict(value=done / t_total, unit="rays/s", cores=cores, kind="oracle",
                 sample=f"{done} strided pixels of the two 1024x1024 a=0.99 images (half each), FP64 DOPRI5 "
-                       f"rtol 1e-8, {t_total:.1f} s wall"), errors
+                       f"rtol 1e-8, {t_total:.1f} s wall",
+                rhs_evals_per_s=rhs / t_total,
+                ns_per_attempt_per_ray_one_core=t_total * cores / attempts * 1e9,
+                host=dict(cpu=model, logical_cpus=os.cpu_count())), errors
 
 
 def precision_only(args):
