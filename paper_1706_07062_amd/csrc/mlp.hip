@@ -204,8 +204,9 @@ __device__ inline void lds_barrier() {
 }
 
 // Inference forward, ping-pong: a block of eight waves holds two groups of
-// four (waves 0-3 and 4-7; wave w of a block runs on SIMD w % 4, so each SIMD
-// holds one wave of each group).  A group carries 128 rays: its wave w
+// four (waves 0-3 and 4-7; the waves of a block go to the four SIMDs in
+// turn, so waves w and w + 4 share a SIMD and each SIMD holds one wave of
+// each group).  A group carries 128 rays: its wave w
 // computes outputs 64 w .. 64 w + 63 of every hidden layer for all 128 rays
 // (2 x 4 accumulator tiles), and the group's activations sit in LDS rows
 // [ray][feature], read by its four waves.  A group's work on one batch is eight steps that
@@ -540,8 +541,6 @@ __global__ void k_mlp_loss(const float* y, const float* t, const uint8_t* mask, 
   }
 }
 
-// Gradient with respect to a layer's input, times SiLU' of the layer below:
-// dz_out[ray][k] = (sum_o dz[ray][o] W[o][k]) * silu'(zprev[ray][k]).
 // Arguments of one layer's backward launch (k_mlp_bwd): its weight-gradient
 // tasks and, except for layer 0, its input-gradient ray tiles.
 struct BwdLayer {
@@ -562,9 +561,11 @@ struct BwdLayer {
   int ndx;  // ray tiles (blocks) of the input gradient, a multiple of 8
 };
 
-// Gradient with respect to a layer's input for ray tile `blk` (one 32-ray
-// tile per block; wave w computes input features 64 w .. 64 w + 63); every
-// fragment is requested before the first product (one wave per SIMD).
+// Gradient with respect to a layer's input, times SiLU' of the layer below,
+// dz_out[ray][k] = (sum_o dz[ray][o] W[o][k]) * silu'(zprev[ray][k]), for ray
+// tile `blk` (one 32-ray tile per block; wave w computes input features
+// 64 w .. 64 w + 63); every fragment is requested before the first product
+// (one wave per SIMD).
 template <int OPAD>
 __device__ inline void bwd_dx_tile(const BwdLayer& L, int blk, int w, int lane) {
   const __bf16* wbt = L.wbt;
