@@ -73,7 +73,8 @@ typedef struct {
   float tau;         /* capture uncertain: tau < p_capture < 1 - tau; tau in [0, 0.5) */
   float shadow_band; /* near the shadow edge: within this distance (M, image plane) of the
                         critical curve of the camera's spin and inclination (Bardeen's closed
-                        form for a distant observer); 0 = off (also for sin(incl) < 1e-3) */
+                        form for a distant observer; a face-on camera, sin(incl) < 1e-3, sees
+                        the circle of the photon orbit with L_z = 0); 0 = off */
   float r_min;       /* strong field: predicted first crossing inside r_min (M) and
                         p_capture <= 1/2, where the crossing radius and the redshift change
                         fastest across the image; 0 = off */

@@ -1011,14 +1011,18 @@ namespace {
 // eta = Q / E^2 from R(r) = R'(r) = 0,
 //   xi = (r^2 (3 - r) - a^2 (r + 1)) / (a (r - 1)),
 //   eta = r^3 (4 a^2 - r (r - 3)^2) / (a^2 (r - 1)^2),
-// and reach the image at alpha = -xi / sin i, beta = +-sqrt(eta + a^2 cos^2 i
-// - xi^2 cot^2 i).  The curve is tabulated as its radius around (ac, 0) in
-// kCritBins equal angle bins (it is star-shaped about that centre); a = 0
-// gives the circle of radius sqrt(27).  Returns false for a face-on camera
-// (sin i < 1e-3), where the formula degenerates; the rule is then off.
+// and reach the image at alpha = -xi / sin i, beta = +-sqrt(b2),
+// b2 = eta + a^2 cos^2 i - xi^2 cot^2 i.  b2 >= 0 holds on one interval of r
+// around the orbit with xi = 0, which narrows as the camera turns face-on;
+// the curve is sampled on that interval (its ends found by bisection, the
+// samples crowded towards them, where beta -> 0) and tabulated as its radius
+// around (ac, 0) in kCritBins equal angle bins (it is star-shaped about that
+// centre).  a = 0 gives the circle of radius sqrt(27); a face-on camera
+// (sin i < 1e-3), which only the xi = 0 orbit reaches, the circle of radius
+// sqrt(eta + a^2) of that orbit.  Returns false if the curve cannot be
+// formed.
 bool critical_curve(double a, double incl, float* ac, float* rad) {
   const double si = std::sin(incl), ci = std::cos(incl);
-  if (std::fabs(si) < 1e-3) return false;
   if (std::fabs(a) < 1e-9) {
     *ac = 0.0f;
     for (int k = 0; k < kCritBins; ++k) rad[k] = (float)std::sqrt(27.0);
@@ -1027,19 +1031,45 @@ bool critical_curve(double a, double incl, float* ac, float* rad) {
   const double aa = std::fabs(a);
   const double r1 = 2.0 * (1.0 + std::cos(2.0 / 3.0 * std::acos(-aa)));
   const double r2 = 2.0 * (1.0 + std::cos(2.0 / 3.0 * std::acos(aa)));
+  auto xi = [&](double r) { return (r * r * (3.0 - r) - a * a * (r + 1.0)) / (a * (r - 1.0)); };
+  auto eta = [&](double r) {
+    return r * r * r * (4.0 * a * a - r * (r - 3.0) * (r - 3.0)) / (a * a * (r - 1.0) * (r - 1.0));
+  };
+  auto b2 = [&](double r) { return eta(r) + a * a * ci * ci - xi(r) * xi(r) * ci * ci / (si * si); };
+  // bisection for the sign change of f on [lo, hi] (f(lo), f(hi) of opposite signs)
+  auto bisect = [](auto f, double lo, double hi) {
+    const bool neg_lo = f(lo) < 0.0;
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if ((f(mid) < 0.0) == neg_lo)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    return 0.5 * (lo + hi);
+  };
+  // the orbit with xi = 0 (xi changes sign between the two photon orbits)
+  const double r0 = bisect([&](double r) { return xi(r); }, r1, r2);
+  if (std::fabs(si) < 1e-3) {
+    const double e0 = eta(r0);
+    if (!(e0 + a * a > 0.0)) return false;
+    *ac = 0.0f;
+    for (int k = 0; k < kCritBins; ++k) rad[k] = (float)std::sqrt(e0 + a * a);
+    return true;
+  }
+  if (!(b2(r0) > 0.0)) return false;
+  const double ra = b2(r1) >= 0.0 ? r1 : bisect(b2, r1, r0);
+  const double rb = b2(r2) >= 0.0 ? r2 : bisect(b2, r0, r2);
   constexpr int n = 4096;
   std::vector<std::pair<double, double>> pts;  // (alpha, beta)
-  pts.reserve(2 * n);
+  pts.reserve(2 * n + 2);
   for (int j = 0; j <= n; ++j) {
-    const double r = r1 + (r2 - r1) * j / n;
-    const double xi = (r * r * (3.0 - r) - a * a * (r + 1.0)) / (a * (r - 1.0));
-    const double eta = r * r * r * (4.0 * a * a - r * (r - 3.0) * (r - 3.0)) / (a * a * (r - 1.0) * (r - 1.0));
-    const double b2 = eta + a * a * ci * ci - xi * xi * ci * ci / (si * si);
-    if (!(b2 >= 0.0)) continue;
-    pts.emplace_back(-xi / si, std::sqrt(b2));
-    pts.emplace_back(-xi / si, -std::sqrt(b2));
+    const double r = ra + (rb - ra) * 0.5 * (1.0 - std::cos(M_PI * j / n));
+    const double q = b2(r);
+    const double bet = q > 0.0 ? std::sqrt(q) : 0.0;
+    pts.emplace_back(-xi(r) / si, bet);
+    pts.emplace_back(-xi(r) / si, -bet);
   }
-  if (pts.size() < 16) return false;
   double amin = pts[0].first, amax = pts[0].first;
   for (const auto& q : pts) {
     amin = std::min(amin, q.first);

@@ -232,15 +232,26 @@ def _critical_distance(cam, al, be):
     """Signed distance (M) of image points from the camera's critical curve,
     from Bardeen's closed form (tests/closed_forms.py), measured along the
     ray from the curve's centre: the curve's radius in the direction of the
-    point by interpolation over a dense sampling of the photon-orbit radius."""
-    from closed_forms import bardeen_alpha, bardeen_beta2, r_prograde_photon, r_retrograde_photon
+    point by interpolation over a dense sampling of the photon-orbit radius on
+    the interval where beta^2 >= 0 (its ends by root finding; the interval
+    closes around the orbit with xi = 0 as the camera turns face-on, and a
+    face-on camera sees that orbit's circle, of radius sqrt(eta + a^2))."""
+    from scipy.optimize import brentq
+
+    from closed_forms import bardeen_alpha, bardeen_beta2, r_prograde_photon, r_retrograde_photon, spherical_xi_eta
 
     if cam.a == 0.0:  # Schwarzschild: the circle of radius sqrt(27)
         return np.hypot(al, be) - np.sqrt(27.0)
-    rs = np.linspace(r_prograde_photon(cam.a), r_retrograde_photon(cam.a), 20001)
-    b2 = np.array([bardeen_beta2(r, cam.a, cam.incl) for r in rs])
-    A = np.array([bardeen_alpha(r, cam.a, cam.incl) for r in rs])[b2 >= 0]
-    B = np.sqrt(b2[b2 >= 0])
+    r1, r2 = r_prograde_photon(cam.a), r_retrograde_photon(cam.a)
+    r0 = brentq(lambda r: spherical_xi_eta(r, cam.a)[0], r1, r2, xtol=1e-15)
+    if abs(np.sin(cam.incl)) < 1e-3:
+        return np.hypot(al, be) - np.sqrt(spherical_xi_eta(r0, cam.a)[1] + cam.a ** 2)
+    b2 = lambda r: bardeen_beta2(r, cam.a, cam.incl)  # noqa: E731
+    ra = r1 if b2(r1) >= 0 else brentq(b2, r1, r0, xtol=1e-15)
+    rb = r2 if b2(r2) >= 0 else brentq(b2, r0, r2, xtol=1e-15)
+    rs = ra + (rb - ra) * 0.5 * (1.0 - np.cos(np.pi * np.linspace(0.0, 1.0, 20001)))
+    A = np.array([bardeen_alpha(r, cam.a, cam.incl) for r in rs])
+    B = np.sqrt(np.maximum([b2(r) for r in rs], 0.0))
     A, B = np.concatenate([A, A]), np.concatenate([B, -B])
     c = 0.5 * (A.max() + A.min())
     th, rad = np.arctan2(B, A - c), np.hypot(A - c, B)
@@ -300,12 +311,14 @@ def test_image_kernel_fallback_rules(ctx):
     assert (ids.cpu().numpy() == -1).all()
 
 
-@pytest.mark.parametrize("a,incl", [(0.0, 60.0), (-0.7, 30.0), (0.998, 80.0)])
+@pytest.mark.parametrize("a,incl", [(0.0, 60.0), (-0.7, 30.0), (0.998, 80.0), (0.9, 0.0), (0.9, 0.3), (-0.5, 1.0)])
 def test_image_kernel_shadow_band_other_cameras(ctx, a, incl):
     """The shadow-edge rule for a Schwarzschild hole (circle of radius
-    sqrt(27)), a negative spin (the mirror image in alpha) and a near-extremal,
-    nearly edge-on camera: the listed pixels are those within the band of the
-    critical curve, up to pixels at the band's edge."""
+    sqrt(27)), a negative spin (the mirror image in alpha), a near-extremal,
+    nearly edge-on camera, a face-on camera (the circle of the orbit with
+    L_z = 0) and two nearly face-on ones, where the part of the photon-orbit
+    range that reaches the image is narrow: the listed pixels are those
+    within the band of the critical curve, up to pixels at the band's edge."""
     say(f"mlp shadow band, a = {a}, incl = {incl}")
     p = _random_biases(S.init_params(17), 28)
     net = K.Mlp(p, train=False)
