@@ -130,6 +130,14 @@ struct FwdArgs {
   float* z;    // training: pre-activations [4][bmax][256]
   __bf16* ht;  // training: HT_0 [32][bmax], then HT_1..HT_4 [256][bmax]
   int64_t bmax;
+  // training loss (k_mlp_fwd_train; dz4 NULL = no loss): targets [m][4],
+  // mask [m], weights; gradient dz4 [bmax][32] and dz4T [32][bmax]; sum
+  const float* t;
+  const uint8_t* mask;
+  kh_mlp_loss_w wl;
+  __bf16* dz4;
+  __bf16* dz4T;
+  float* loss;
 };
 
 __host__ __device__ inline __bf16* ht_layer(__bf16* ht, int l, int64_t bmax) {
@@ -397,6 +405,30 @@ k_mlp_fwd_pp(FwdArgs A, int32_t nb) {
   flush_fallback();
 }
 
+// Loss of one ray and its gradient with respect to the raw outputs, written
+// as the BF16 row dz [32] (columns 4..31 zero) and column dzT [32][bmax]:
+// mask bit 0: w.r (y0 - t0)^2 + w.phi (y1 - t1)^2; mask bit 1: w.g (y2 - t2)^2;
+// always w.capture BCE(sigmoid(y3), t3); the mean over the b rays of the batch.
+__device__ inline float ray_loss(const f32x4& yv, const f32x4& tv, int mk, int64_t b, const kh_mlp_loss_w& wl,
+                                 __bf16* dz, __bf16* dzT, int64_t bmax, int64_t i) {
+  const float inv = 1.0f / (float)b;
+  const float e0 = (mk & 1) ? yv[0] - tv[0] : 0.0f;
+  const float e1 = (mk & 1) ? yv[1] - tv[1] : 0.0f;
+  const float e2 = (mk & 2) ? yv[2] - tv[2] : 0.0f;
+  const float s = sigmoidf(yv[3]);
+  const float bce = fmaxf(yv[3], 0.0f) - yv[3] * tv[3] + log1pf(__expf(-fabsf(yv[3])));
+  const float l = wl.r * (e0 * e0) + wl.phi * (e1 * e1) + wl.g * (e2 * e2) + wl.capture * bce;
+  const float d[4] = {2.0f * wl.r * e0 * inv, 2.0f * wl.phi * e1 * inv, 2.0f * wl.g * e2 * inv,
+                      wl.capture * (s - tv[3]) * inv};
+#pragma unroll
+  for (int c = 0; c < 32; ++c) {
+    const __bf16 v = (__bf16)(c < 4 ? d[c] : 0.0f);
+    dz[i * 32 + c] = v;
+    dzT[(int64_t)c * bmax + i] = v;
+  }
+  return l;
+}
+
 // Training forward for batches of a few thousand rays: a block of four waves
 // carries one tile of 32 rays and each wave computes 64 of a layer's 256
 // outputs (two accumulator tiles), so a batch of b rays keeps b / 8 waves
@@ -422,35 +454,56 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
     for (int j = 0; j < 16; ++j)
       ht0[(int64_t)(16 * half + j) * A.bmax + ray] = (half == 0 && j < 4) ? (__bf16)f[j & 3] : (__bf16)0.0f;
   }
+  // the targets of the loss, requested long before the output layer needs them
+  f32x4 tv = {0.f, 0.f, 0.f, 0.f};
+  int mk = 0;
+  if (A.dz4 && w == 0 && half == 0 && valid) {
+    tv = *reinterpret_cast<const f32x4*>(A.t + ray * 4);
+    mk = A.mask[ray];
+  }
+  // A batch keeps one wave per SIMD busy, so nothing hides a load's latency:
+  // all 32 weight fragments of a layer are requested together, those of the
+  // next layer as soon as this layer's products are issued (they arrive during
+  // the epilogue and the barrier).
+  bf16x8 aw[HID / 16][2];
+  auto load_layer = [&](int l) {
+    const __bf16* wl = A.wb + (l == 1 ? OFF_WB[1] : l == 2 ? OFF_WB[2] : OFF_WB[3]);
+#pragma unroll
+    for (int ks = 0; ks < HID / 16; ++ks)
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt)
+        aw[ks][tt] = *reinterpret_cast<const bf16x8*>(wl + wb_index(HID, (2 * w + tt) * 32 + r, ks * 16 + 8 * half));
+  };
+  load_layer(1);
   const f32x16 zero = {};
   f32x16 acc[2];
 #pragma unroll
   for (int tt = 0; tt < 2; ++tt) {
     const int t = 2 * w + tt;
-    const bf16x8 aw = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[0] + (t * 32 + r) * KPAD[0] + 8 * half);
-    acc[tt] = mfma(aw, bx, zero);
+    const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[0] + (t * 32 + r) * KPAD[0] + 8 * half);
+    acc[tt] = mfma(a0, bx, zero);
   }
+#pragma unroll
   for (int l = 0; l < 4; ++l) {
     if (l > 0) {
       const __bf16* in = act[(l - 1) & 1];
-      const __bf16* wl = A.wb + (l == 1 ? OFF_WB[1] : l == 2 ? OFF_WB[2] : OFF_WB[3]);
 #pragma unroll
       for (int tt = 0; tt < 2; ++tt) acc[tt] = zero;
-      // a batch keeps one wave per SIMD busy, so nothing hides a load's
-      // latency: all 32 weight fragments of the layer are requested first
-      bf16x8 aw[HID / 16][2];
-#pragma unroll
-      for (int ks = 0; ks < HID / 16; ++ks)
-#pragma unroll
-        for (int tt = 0; tt < 2; ++tt)
-          aw[ks][tt] = *reinterpret_cast<const bf16x8*>(wl + wb_index(HID, (2 * w + tt) * 32 + r, ks * 16 + 8 * half));
-      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int ks = 0; ks < HID / 16; ++ks) {
         const bf16x8 bv = *reinterpret_cast<const bf16x8*>(in + r * LDA + ks * 16 + 8 * half);
 #pragma unroll
         for (int tt = 0; tt < 2; ++tt) acc[tt] = mfma(aw[ks][tt], bv, acc[tt]);
       }
+      __builtin_amdgcn_sched_barrier(0);
+      if (l < 3) {
+        load_layer(l + 1);
+      } else if (w == 0) {
+#pragma unroll
+        for (int ks = 0; ks < HID / 16; ++ks)
+          aw[ks][0] = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + wb_index(32, r, ks * 16 + 8 * half));
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     // bias, SiLU, the next activation rows and the saved tensors of this wave's outputs
     const float* bias = A.params + OFF_B[l];
@@ -480,64 +533,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
     __syncthreads();  // the layer's activation rows are complete
   }
 
-  // output layer (256 -> 4, padded to 32 rows), one wave
+  // output layer (256 -> 4, padded to 32 rows), one wave; then the loss of
+  // the tile's rays and its gradient with respect to the raw outputs
   if (w == 0) {
     const __bf16* in = act[1];
     f32x16 o = zero;
-    bf16x8 aw[HID / 16];
-#pragma unroll
-    for (int ks = 0; ks < HID / 16; ++ks)
-      aw[ks] = *reinterpret_cast<const bf16x8*>(A.wb + OFF_WB[4] + wb_index(32, r, ks * 16 + 8 * half));
-    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ks = 0; ks < HID / 16; ++ks) {
       const bf16x8 bv = *reinterpret_cast<const bf16x8*>(in + r * LDA + ks * 16 + 8 * half);
-      o = mfma(aw[ks], bv, o);
+      o = mfma(aw[ks][0], bv, o);
     }
+    float lsum = 0.0f;
     if (half == 0 && valid) {
       const float* b4 = A.params + OFF_B[4];
       f32x4 y;
 #pragma unroll
       for (int q = 0; q < 4; ++q) y[q] = o[q] + b4[q];
       *reinterpret_cast<f32x4*>(A.y + ray * 4) = y;
+      if (A.dz4) lsum = ray_loss(y, tv, mk, A.m, A.wl, A.dz4, A.dz4T, A.bmax, ray);
     }
-  }
-}
-
-// Loss and its gradient with respect to the raw outputs; dz [bmax][32] and
-// dzT [32][bmax] (BF16, columns / rows 4..31 zero).
-__global__ void k_mlp_loss(const float* y, const float* t, const uint8_t* mask, int64_t b, kh_mlp_loss_w wl,
-                           __bf16* dz, __bf16* dzT, int64_t bmax, float* loss) {
-  __shared__ float part[4];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  float l = 0.0f;
-  if (i < b) {
-    const f32x4 yv = *reinterpret_cast<const f32x4*>(y + i * 4);
-    const f32x4 tv = *reinterpret_cast<const f32x4*>(t + i * 4);
-    const int mk = mask[i];
-    const float inv = 1.0f / (float)b;
-    const float e0 = (mk & 1) ? yv[0] - tv[0] : 0.0f;
-    const float e1 = (mk & 1) ? yv[1] - tv[1] : 0.0f;
-    const float e2 = (mk & 2) ? yv[2] - tv[2] : 0.0f;
-    const float s = sigmoidf(yv[3]);
-    const float bce = fmaxf(yv[3], 0.0f) - yv[3] * tv[3] + log1pf(__expf(-fabsf(yv[3])));
-    l = wl.r * (e0 * e0) + wl.phi * (e1 * e1) + wl.g * (e2 * e2) + wl.capture * bce;
-    const float d[4] = {2.0f * wl.r * e0 * inv, 2.0f * wl.phi * e1 * inv, 2.0f * wl.g * e2 * inv,
-                        wl.capture * (s - tv[3]) * inv};
-#pragma unroll
-    for (int c = 0; c < 32; ++c) {
-      const __bf16 v = (__bf16)(c < 4 ? d[c] : 0.0f);
-      dz[i * 32 + c] = v;
-      dzT[(int64_t)c * bmax + i] = v;
+    if (A.dz4) {
+      for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off);
+      if (lane == 0) atomicAdd(A.loss, lsum / (float)A.m);
     }
-  }
-  for (int off = 32; off > 0; off >>= 1) l += __shfl_down(l, off);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float s = 0.0f;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
-    atomicAdd(loss, s / (float)b);
   }
 }
 
@@ -880,9 +898,13 @@ kh_status grad_pass(kh_ctx* ctx, const kh_mlp* net, void* work, int32_t max_batc
   A.z = w.z;
   A.ht = w.ht;
   A.bmax = bmax;
+  A.t = t;
+  A.mask = mask;
+  A.wl = wl;
+  A.dz4 = w.dz4;
+  A.dz4T = w.dz4T;
+  A.loss = loss;
   hipLaunchKernelGGL(k_mlp_fwd_train, dim3((unsigned)(b / RAYS)), dim3(256), 0, strm, A);
-  hipLaunchKernelGGL(k_mlp_loss, dim3((unsigned)(b / 256)), dim3(256), 0, strm, w.y, t, mask, (int64_t)b, wl,
-                     w.dz4, w.dz4T, bmax, loss);
   const __bf16* wbt = reinterpret_cast<const __bf16*>(net->wbt);
   auto ht = [&](int l) { return ht_layer(w.ht, l, bmax); };
   auto zl = [&](int l) { return w.z + (int64_t)l * bmax * HID; };
