@@ -470,11 +470,41 @@ class State:
                           p(self.status), p(self.n_acc), p(self.n_rej), p(self.cross), p(self.n_cross), k_cross,
                           p(self.c0), p(self.c1), p(self.order), n_out, p(self.t_out), p(self.s_out), p(self.perm))
 
+    _ARRAYS = ("s", "spin", "kind", "h", "lam", "phi", "status", "n_acc", "n_rej", "cross", "n_cross", "c0", "c1",
+               "order", "t_out", "s_out", "perm")
+
     def numpy(self) -> dict:
         """Host copy of every array (for checks; synchronises)."""
         out = {}
-        for name in ("s", "spin", "kind", "h", "lam", "phi", "status", "n_acc", "n_rej", "cross", "n_cross", "c0",
-                     "c1", "order", "s_out", "perm"):
+        for name in self._ARRAYS:
+            if name == "t_out":
+                continue
             t = getattr(self, name)
             out[name] = t.cpu().numpy() if t is not None else None
         return out
+
+    def save(self, path) -> None:
+        """Checkpoint: every array of the state (positions and momenta, step
+        sizes, affine parameters, statuses, counters, crossing records,
+        constants, schedule, dense output) to one .npz file.  The state is the
+        whole of an integration's progress, so State.load(path) followed by
+        kh_integrate continues bitwise as the uninterrupted run would."""
+        import numpy as np
+
+        arrays = {name: getattr(self, name).cpu().numpy() for name in self._ARRAYS if getattr(self, name) is not None}
+        np.savez(path, n=np.int64(self.n), k_cross=np.int64(self.k_cross), **arrays)
+
+    @classmethod
+    def load(cls, path, device="cuda") -> "State":
+        """A State holding a checkpoint written by save() (plain arrays, read
+        without unpickling)."""
+        import numpy as np
+
+        with np.load(path, allow_pickle=False) as d:
+            schedule = "geodesics" if "perm" in d.files else ("tiles" if "order" in d.files else None)
+            st = cls(int(d["n"]), k_cross=int(d["k_cross"]), constants="c0" in d.files, device=device,
+                     schedule=schedule, t_out=d["t_out"] if "t_out" in d.files else None)
+            for name in cls._ARRAYS:
+                if name in d.files:
+                    getattr(st, name).copy_(torch.from_numpy(d[name]))
+        return st

@@ -324,6 +324,53 @@ def test_resume_is_bitwise(ctx):
     assert np.array_equal(np.nan_to_num(g["cross"], nan=-7.0), np.nan_to_num(ref["cross"], nan=-7.0))
 
 
+def test_resume_from_a_checkpoint_file_is_bitwise(ctx, tmp_path):
+    """The state is the checkpoint: pause a particle set (per-geodesic
+    schedule, constants, dense output) and an image (tile order, crossing
+    records) after 40 accepted steps, write the state to disk, load it into a
+    new State in a fresh context and finish: bitwise the uninterrupted run."""
+    say("resume from a checkpoint file")
+    pw = W.particles()
+    idx = np.arange(0, 1 << 20, 8191)[:128]
+    t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()  # noqa: E731
+    cam = W.kerr_image(17.0, side=32)
+    cases = []
+    for kind in ("particles", "image"):
+        if kind == "particles":
+            mk = lambda: K.State(len(idx), schedule="geodesics", t_out=[10.0, 500.0, 5000.0])  # noqa: E731
+            init = lambda c, s: c.kh_init_geodesics(K.TIMELIKE, t(pw["a"][idx]), t(pw["x3"][:, idx]),  # noqa: E731
+                                                     t(pw["v3"][:, idx]), s)
+            prm = dict(t_end=1e4, r_escape=1e4)
+        else:
+            mk = lambda: K.State(cam.n, k_cross=4)  # noqa: E731
+            init = lambda c, s: c.kh_init_rays([kcam(cam)], s)  # noqa: E731
+            prm = dict(k_cross=4)
+        ref = mk()
+        init(ctx, ref)
+        ctx.kh_integrate(K.kh_default_params(**prm), ref)
+        st = mk()
+        init(ctx, st)
+        ctx.kh_integrate(K.kh_default_params(max_steps=40, **prm), st)
+        torch.cuda.synchronize()
+        assert ctx.kh_stats(st)["status_counts"][K.MAX_STEPS] > 0
+        path = tmp_path / f"{kind}.npz"
+        st.save(path)
+        cases.append((kind, path, prm, ref.numpy()))
+    ctx2 = K.Context(0)
+    try:
+        for kind, path, prm, want in cases:
+            st2 = K.State.load(path)
+            ctx2.kh_integrate(K.kh_default_params(**prm), st2)
+            got = st2.numpy()
+            say(f"  {kind}: statuses {np.bincount(got['status'], minlength=6).tolist()}")
+            for name, a in got.items():
+                if a is None or name in ("order", "perm"):
+                    continue
+                assert np.array_equal(np.nan_to_num(a, nan=-7.0), np.nan_to_num(want[name], nan=-7.0)), (kind, name)
+    finally:
+        ctx2.close()
+
+
 def test_launch_shape_does_not_change_results(ctx):
     """Each lane's arithmetic is independent of scheduling: block size, grid size
     and refill threshold give bitwise identical FP64 results."""
