@@ -361,8 +361,12 @@ def surrogate_extra(ctx, K, W, torch, args):
     # shadow-edge and strong-field rules
     for tau, band, r_min in ((0.45, 0.0, 0.0), (0.2, 0.0, 0.0), (0.05, 0.0, 0.0), (0.01, 0.0, 0.0),
                              (0.2, 0.1, 0.0), (0.2, 0.3, 0.0), (0.2, 0.3, 3.0), (0.05, 0.3, 4.0)):
-        sur.render(cam, tau, shadow_band=band, r_min=r_min)  # warm-up
-        img, tm = sur.render(cam, tau, shadow_band=band, r_min=r_min)
+        # the clocks settle over the first launches of a new kernel: three
+        # untimed renders, then the median of five (the outputs are identical)
+        for _ in range(3):
+            sur.render(cam, tau, shadow_band=band, r_min=r_min)
+        runs = [sur.render(cam, tau, shadow_band=band, r_min=r_min) for _ in range(5)]
+        img, tm = sorted(runs, key=lambda rt: rt[1]["total_s"])[2]
         err = S.image_error(img, ref)
         curve.append(dict(tau=tau, shadow_band=band, r_min=r_min, speedup=t_int / tm["total_s"], **tm, **err))
         log(f"surrogate tau {tau} band {band} r_min {r_min}: speedup {t_int / tm['total_s']:.2f}, fallback "
