@@ -126,7 +126,7 @@ typedef struct {
 
 /* Integration rules.  Defaults (kh_default_params): DOPRI5, FP64,
  * h_coeff 0.01, rtol = atol = 1e-8, hmax_coeff 0.1, r_h_factor 1.01,
- * r_escape 1000, t_end 0 (off), r_fp64 3, max_steps 1e6. */
+ * r_escape 1000, t_end 0 (off), r_fp64 3, max_steps 1e6, mixed_split 0. */
 typedef struct {
   int32_t method;    /* KH_RK4 (fixed step h = h_coeff * r), KH_DOPRI5, or KH_DOPRI5_T: Dormand-Prince in
                         coordinate time (below) */
@@ -139,18 +139,27 @@ typedef struct {
   double r_h_factor; /* capture radius factor, r_H = 1 + sqrt(1 - a^2) */
   double r_escape;   /* escape radius */
   double t_end;      /* > 0: stop and land on x^0 = t_end (DOPRI5 only) */
-  double r_fp64;     /* KH_PMIXED: FP64 right-hand side when any lane of the wave has r < r_fp64 */
+  double r_fp64;     /* KH_PMIXED: the radius inside which right-hand sides are evaluated in FP64 (by the whole
+                        wave, or by the second pass of the two-queue split; see mixed_split) */
   int64_t max_steps; /* accepted steps per call before KH_MAX_STEPS (> 0) */
   int32_t block_size;   /* threads per block: 64, 128, 192 or 256; 0 = 256 */
   int32_t grid_blocks;  /* persistent grid size; 0 = fill the device from the occupancy query */
   int32_t refill_min;   /* a wave refills once at least this many lanes are idle (1..64); 0 = 12 */
   int32_t waves_per_eu; /* register budget of the kernel variant (minimum waves per SIMD): 1 = two or more
-                           waves; DOPRI5 with the factored form also has 3 and 4 (FP64 / mixed) and 4 and 5
-                           (FP32); 0 = default (3 for mixed-precision DOPRI5, else 1) */
+                           waves; DOPRI5 with the factored form also has 3 and 4 (FP64 / mixed; 3 only for the
+                           first pass of the two-queue split, whose FP64 pass always uses 1) and 4 and 5 (FP32);
+                           coordinate-time mixed has 3; 0 = default (3 for mixed-precision DOPRI5, else 1) */
   int32_t queue_parts;  /* work-queue partitions of the ray range (1..8); 0 = 8, one per XCD: chunks of 8192
                            ids are dealt round-robin to the partitions, a wave starts on its XCD's partition
                            and steals from the others when it is drained */
-  int32_t reserved;
+  int32_t mixed_split;  /* KH_PMIXED with a DOPRI5 method: 0 = per-wave switch (a wave evaluates its right-hand
+                           sides and stage sums in FP64 while any of its lanes is inside r_fp64, else in FP32);
+                           1 = two-queue split: a first pass integrates every geodesic with FP32 right-hand sides
+                           and stage sums until it comes inside r_fp64, where it is parked, and a second pass
+                           continues the parked geodesics in FP64 to the end of the call (two launches and two
+                           finalize passes on the stream).  With 1 each geodesic's result depends on no other
+                           geodesic, as in FP64 and FP32; max_steps and the attempt limit apply to each pass.
+                           Must be 0 for other precisions (KH_EINVAL) and for KH_RK4 (KH_EUNSUPPORTED). */
 } kh_params;
 /* KH_DOPRI5_T (the coordinate-time subsection of Sec. 2.2): the six-variable
  * state (x^i, v^i = dx^i/dt) is integrated in t with dv^i/dt = a^i - a^0 v^i,

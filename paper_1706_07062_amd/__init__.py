@@ -45,7 +45,7 @@ class kh_params(C.Structure):
                 ("r_h_factor", C.c_double), ("r_escape", C.c_double), ("t_end", C.c_double),
                 ("r_fp64", C.c_double), ("max_steps", C.c_int64), ("block_size", C.c_int32),
                 ("grid_blocks", C.c_int32), ("refill_min", C.c_int32), ("waves_per_eu", C.c_int32),
-                ("queue_parts", C.c_int32), ("reserved", C.c_int32)]
+                ("queue_parts", C.c_int32), ("mixed_split", C.c_int32)]
 
 
 class kh_flop_counts(C.Structure):

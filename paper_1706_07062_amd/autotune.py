@@ -4,9 +4,12 @@ The paper's framework benchmarks alternative implementations at run time and
 keeps the fastest (Sec. 2.3, and Sec. 4's work-group-size tuning).  Here the
 alternatives are launch shapes of the persistent kernel: threads per block,
 register budget (kernel variant with a minimum waves-per-SIMD target) and the
-refill threshold.  For FP64 and FP32 they change only the schedule, never a
-result (each lane's arithmetic is fixed), so tuning is safe; MIXED results
-depend on which rays share a wave.
+refill threshold, and for MIXED DOPRI5 the policy that places the FP64
+right-hand sides (per-wave switch or two-queue split, `mixed_split`).  For
+FP64, FP32 and the two-queue split the launch shape changes only the
+schedule, never a result (each lane's arithmetic is fixed), so tuning is
+safe; per-wave-switch MIXED results depend on which rays share a wave, and
+the two policies give results that differ within the mixed tolerance.
 
 Usage: ``best = tune(ctx, reinit, state, params, key)`` where ``reinit()``
 re-initialises ``state`` to the tuning sample before each timed run.  The
@@ -26,15 +29,21 @@ from . import DOPRI5, P32, P64, PMIXED, RHS_FACTORED, kh_params
 CACHE_ENV = "KERRHIP_TUNE_CACHE"
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "kerrhip_autotune.json")
 
-# waves-per-SIMD register budgets compiled for each precision (DOPRI5, factored RHS)
+# waves-per-SIMD register budgets compiled for each precision (DOPRI5, factored
+# RHS); MIXED under the two-queue split has the first two
 WAVE_VARIANTS = {P64: (1, 3, 4), P32: (1, 4, 5), PMIXED: (1, 3, 4)}
+SPLIT_WAVE_VARIANTS = (1, 3)
 
 
 def candidates(params: kh_params):
-    waves = WAVE_VARIANTS.get(params.precision, (1,)) if (params.method == DOPRI5 and
-                                                          params.rhs_form == RHS_FACTORED) else (1,)
-    for block, wpe, refill in itertools.product((64, 128, 256), waves, (4, 8, 12, 16)):
-        yield dict(block_size=block, waves_per_eu=wpe, refill_min=refill)
+    dp5_factored = params.method == DOPRI5 and params.rhs_form == RHS_FACTORED
+    splits = (0, 1) if (params.precision == PMIXED and params.method == DOPRI5) else (params.mixed_split,)
+    for split in splits:
+        waves = WAVE_VARIANTS.get(params.precision, (1,)) if dp5_factored else (1,)
+        if split:
+            waves = SPLIT_WAVE_VARIANTS
+        for block, wpe, refill in itertools.product((64, 128, 256), waves, (4, 8, 12, 16)):
+            yield dict(block_size=block, waves_per_eu=wpe, refill_min=refill, mixed_split=split)
 
 
 def _device_key():

@@ -37,6 +37,16 @@ namespace {
 constexpr int kQueueSlots = 16;  // work-queue counters per context
 // Status flags that live only between the integrate kernel and its finalize pass.
 constexpr int kRetired = 0x100, kPhiPending = 0x200, kStatusMask = 0xff;
+// Status of a geodesic that the first pass of the two-queue mixed policy
+// paused after max_steps; the second pass loads only KH_ACTIVE and
+// KH_MAX_STEPS geodesics, so these wait out that pass and its finalize pass
+// turns them into KH_MAX_STEPS.  No call returns with it.
+constexpr int kPaused = 6;
+// Kernel-template precision of the first pass of the two-queue mixed policy
+// (FP64 state and error norm, FP32 right-hand sides and stage sums for every
+// geodesic; one inside r_fp64 is written back for the FP64 pass).  Not a
+// kh_params.precision value.
+constexpr int kPSplit = 3;
 constexpr int kParts = 8;        // ray-range partitions = XCDs of an MI355X
 
 __device__ inline double hscale(int kind, double r) { return kind == KH_TIMELIKE ? r * ksqrt(r) : r; }
@@ -206,7 +216,7 @@ __device__ inline void flush_crossings(double* q, int* qcnt, int count, const KS
 
 // ---------------------------------------------------------------------------
 // Persistent integrate kernel.
-// METHOD: KH_RK4 / KH_DOPRI5 / KH_DOPRI5_T (coordinate time).  PREC: KH_P64 / KH_P32 / KH_PMIXED.
+// METHOD: KH_RK4 / KH_DOPRI5 / KH_DOPRI5_T (coordinate time).  PREC: KH_P64 / KH_P32 / KH_PMIXED / kPSplit.
 // FORM: right-hand-side evaluation (KH_RHS_FACTORED / KH_RHS_PAPER).
 // ---------------------------------------------------------------------------
 // WPE: minimum waves per SIMD the register allocation must allow (1 = no limit).
@@ -284,7 +294,8 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
     // the finalize pass adds atan2(y, x) to the winding part and clears the
     // flags; without crossings the azimuth is not tracked and phi is left as is
     if (P.k_cross > 0) S.phi[ray] = (2.0 * M_PI) * wind;
-    S.status[ray] = status | kRetired | (P.k_cross > 0 ? kPhiPending : 0);
+    const int st_out = (PREC == kPSplit && status == KH_MAX_STEPS) ? kPaused : status;
+    S.status[ray] = st_out | kRetired | (P.k_cross > 0 ? kPhiPending : 0);
     S.n_acc[ray] = nacc;
     S.n_rej[ray] = nrej;
     if (S.n_cross) S.n_cross[ray] = ncross;
@@ -428,6 +439,10 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
       // ballots count all 64 lanes; each ray retires within max_tries
       // attempts, hence all lanes become idle and the loop ends.
       while (true) {
+        // two-queue mixed policy, first pass: a geodesic inside r_fp64 is
+        // written back as KH_ACTIVE for the FP64 pass, so every attempt of this
+        // pass runs in FP32
+        if (PREC == kPSplit && ray >= 0 && r_cur < (TS)P.r_fp64) retire();
         if (ray >= 0) {
           TS xn[4], kn[4], a7[4], r_new, rdot_new;
           // coordinate time: a step that would pass t_end is clipped onto it
@@ -436,7 +451,7 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
           const TS hs = (TS)hd;
           const TS rtol = (TS)P.rtol, atol = (TS)P.atol;
           TS err2;  // squared RMS error norm
-          if (PREC == KH_PMIXED && __ballot(r_cur < (TS)P.r_fp64) == 0ull)
+          if (PREC == kPSplit || (PREC == KH_PMIXED && __ballot(r_cur < (TS)P.r_fp64) == 0ull))
             err2 = dp5_attempt<FORM, TS, TF, CT, TF>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
           else
             err2 = dp5_attempt<FORM, TS, TS, CT>(a_c, x, k, a1, hs, rtol, atol, xn, kn, a7, r_new, rdot_new);
@@ -590,11 +605,16 @@ k_integrate(KParams P, KState S, unsigned long long* qctr) {
 // Finalize the rays an integrate call retired (flagged in their status), fully
 // parallel: the unwrapped azimuth's atan2(y, x) term and the constants of
 // motion in FP64 are done here rather than in the divergent retire path.
-__global__ void k_finalize(KState S) {
+// unpause: the last pass of a two-queue mixed call (kPaused -> KH_MAX_STEPS).
+__global__ void k_finalize(KState S, int unpause) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = S.n;
   if (i >= n) return;
   const int st = S.status[i];
+  if (unpause && st == kPaused) {
+    S.status[i] = KH_MAX_STEPS;
+    return;
+  }
   if (!(st & kRetired)) return;
   double x[4], k[4];
 #pragma unroll
@@ -1113,6 +1133,8 @@ void* pick_kernel(int method, int prec, int form, int wpe, bool dense) {
     KH_PICKD(KH_DOPRI5_T, KH_P64)
     KH_PICKD(KH_DOPRI5_T, KH_P32)
     KH_PICKD(KH_DOPRI5_T, KH_PMIXED)
+    KH_PICKD(KH_DOPRI5, kPSplit)
+    KH_PICKD(KH_DOPRI5_T, kPSplit)
 #undef KH_PICKD
     return nullptr;
   }
@@ -1138,6 +1160,10 @@ void* pick_kernel(int method, int prec, int form, int wpe, bool dense) {
   KH_PICK(KH_DOPRI5_T, KH_P32, KH_RHS_FACTORED, 1)
   KH_PICK(KH_DOPRI5_T, KH_PMIXED, KH_RHS_FACTORED, 1)
   KH_PICK(KH_DOPRI5_T, KH_PMIXED, KH_RHS_FACTORED, 3)
+  KH_PICK(KH_DOPRI5, kPSplit, KH_RHS_FACTORED, 1)
+  KH_PICK(KH_DOPRI5, kPSplit, KH_RHS_FACTORED, 3)
+  KH_PICK(KH_DOPRI5_T, kPSplit, KH_RHS_FACTORED, 1)
+  KH_PICK(KH_DOPRI5_T, kPSplit, KH_RHS_FACTORED, 3)
 #undef KH_PICK
   return nullptr;
 }
@@ -1442,6 +1468,12 @@ const char* params_problem(const kh_params* p, const kh_state* st, kh_status* co
     *code = KH_EUNSUPPORTED;
     return "crossing records and t_end landing are not combined";
   }
+  if (p->mixed_split != 0 && p->mixed_split != 1) return "mixed_split must be 0 or 1";
+  if (p->mixed_split == 1 && p->precision != KH_PMIXED) return "mixed_split applies to KH_PMIXED only";
+  if (p->mixed_split == 1 && p->method == KH_RK4) {
+    *code = KH_EUNSUPPORTED;
+    return "the two-queue mixed policy needs a DOPRI5 method";
+  }
   if (p->rhs_form == KH_RHS_PAPER && p->precision == KH_PMIXED) {
     *code = KH_EUNSUPPORTED;
     return "the paper-form right-hand side is built for P64 and P32 only";
@@ -1502,35 +1534,47 @@ kh_status launch_integrate(const kh_params* p, const kh_state* st, hipStream_t s
   kp.k_cross = p->k_cross;
   kp.refill_min = p->refill_min ? p->refill_min : 12;
   kp.parts = p->queue_parts ? p->queue_parts : kParts;
+  const bool split = p->precision == KH_PMIXED && p->mixed_split == 1;
 
   // Default register budget: MIXED DOPRI5 runs faster at three waves per SIMD
   // (spilling a few registers) than at two; FP64 and FP32 do not gain.
   int wpe = p->waves_per_eu;
   if (wpe == 0) wpe = (p->method != KH_RK4 && p->precision == KH_PMIXED && p->rhs_form == KH_RHS_FACTORED) ? 3 : 1;
-  void* fn = pick_kernel(p->method, p->precision, p->rhs_form, wpe, st->n_out > 0);
-  if (!fn) {
+  void* fn = pick_kernel(p->method, split ? kPSplit : p->precision, p->rhs_form, wpe, st->n_out > 0);
+  // the second pass of the two-queue policy: the FP64 kernel of the same method
+  void* fn64 = split ? pick_kernel(p->method, KH_P64, p->rhs_form, 1, st->n_out > 0) : nullptr;
+  if (!fn || (split && !fn64)) {
     *msg = "no kernel for this method / precision / rhs_form / waves_per_eu";
     return KH_EUNSUPPORTED;
   }
   // dynamic LDS: one crossing queue (kQFields x kQCap doubles + a counter) per wave
   const size_t lds = p->k_cross > 0 ? (size_t)(block / 64) * (kQFields * kQCap + 1) * sizeof(double) : 0;
-  int grid = p->grid_blocks;
-  if (grid == 0) {
-    int per_cu = 0;
-    KH_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, block, lds));
-    grid = std::max(1, per_cu) * n_cu;
-  }
-  const int64_t need = (st->n + block - 1) / block;
-  if (grid > need) grid = (int)need;
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, strm, q, kParts);
-  KH_TRY(hipGetLastError());
   const KState ks = to_k(st);
-  void* args[] = {(void*)&kp, (void*)&ks, (void*)&q};
-  KH_TRY(hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, strm));
-  const int b = 256;
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((st->n + b - 1) / b)), dim3(b), 0, strm, ks);
-  KH_TRY(hipGetLastError());
-  return KH_OK;
+  // one pass: counter reset, the persistent kernel, the finalize pass
+  auto pass = [&](void* f, KParams& kpp, int unpause) -> kh_status {
+    int grid = p->grid_blocks;
+    if (grid == 0) {
+      int per_cu = 0;
+      KH_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)f, block, lds));
+      grid = std::max(1, per_cu) * n_cu;
+    }
+    const int64_t need = (st->n + block - 1) / block;
+    if (grid > need) grid = (int)need;
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, strm, q, kParts);
+    KH_TRY(hipGetLastError());
+    KState kss = ks;
+    void* args[] = {(void*)&kpp, (void*)&kss, (void*)&q};
+    KH_TRY(hipLaunchKernel(f, dim3(grid), dim3(block), args, lds, strm));
+    const int b = 256;
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((st->n + b - 1) / b)), dim3(b), 0, strm, ks, unpause);
+    KH_TRY(hipGetLastError());
+    return KH_OK;
+  };
+  kh_status s = pass(fn, kp, 0);
+  if (s != KH_OK || !split) return s;
+  // The parked geodesics resume in FP64 from the state the first pass wrote
+  // (its finalize pass completed their azimuth, as for a pause).
+  return pass(fn64, kp, 1);
 }
 
 #undef KH_TRY

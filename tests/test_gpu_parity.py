@@ -11,7 +11,8 @@ import torch
 import oracle as O
 import paper_1706_07062_amd as K
 from paper_1706_07062_amd import workloads as W
-from parity_util import (POS_TOL, compare, gpu_image, kcam, oracle_image, oracle_params, rel_pos)
+from parity_util import (POS_TOL, compare, gpu_image, kcam, oracle_image, oracle_params,
+                         reduced_precision_errors, rel_pos)
 
 pytestmark = pytest.mark.gpu
 
@@ -256,27 +257,6 @@ def test_kerr_1024_both_inclinations_sampled(ctx):
         assert rep["ill"] < 0.02 * rep["n"]
         well = ~o["ill"]
         assert np.array_equal(g["n_cross"][pix + j * cam.n][well], o["n_cross"][well])
-
-
-def reduced_precision_errors(g, o, idx):
-    """Step-independent errors of a reduced-precision run against FP64: status,
-    first equatorial crossing (r, g; interpolated at z = 0, so independent of
-    where the steps fall) and the escape direction k^i/|k|.  Final positions
-    are not comparable: an escaping ray stops anywhere within its last step
-    (up to 0.1 r), and different step sequences stop at different places."""
-    gs, gst = g["s"][:, idx], g["status"][idx]
-    agree = float(np.mean(gst == o["status"]))
-    both = (g["n_cross"][idx] > 0) & (o["n_cross"] > 0)
-    cr = np.abs(g["cross"][idx, 0, 0] - o["cross"][:, 0, 0])[both] / o["cross"][both, 0, 0]
-    okg = both & ~np.isnan(o["cross"][:, 0, 2])
-    cg = np.abs(g["cross"][idx, 0, 2] - o["cross"][:, 0, 2])[okg] / o["cross"][okg, 0, 2]
-    esc = (gst == K.ESCAPED) & (o["status"] == K.ESCAPED)
-    ug = gs[5:8, esc] / np.linalg.norm(gs[5:8, esc], axis=0)
-    uo = o["s"][5:8, esc] / np.linalg.norm(o["s"][5:8, esc], axis=0)
-    ang = np.arccos(np.clip(np.sum(ug * uo, axis=0), -1, 1))
-    return dict(status_agree=agree, cross_r_median=float(np.median(cr)), cross_r_p99=float(np.quantile(cr, 0.99)),
-                cross_g_median=float(np.median(cg)), escape_angle_median=float(np.median(ang)),
-                escape_angle_p99=float(np.quantile(ang, 0.99)))
 
 
 @pytest.mark.parametrize("prec", [K.P32, K.PMIXED])
