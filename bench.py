@@ -51,9 +51,9 @@ def kernel_source_hash():
 # (FETCH_SIZE, WRITE_SIZE, calibrated against a plain copy) and hardware FP64
 # FLOP per launch (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes), valid only for the
 # kernel source they were taken on.
-PROFILED = {"source_hash": "1db49e9bee2b5a28",
-            "traffic_bytes": (120765.0 * 2.0 + 318385.0 * 1.0) * 1024,
-            "hw_fp64_flops": 5801150000.0 * 64}
+PROFILED = {"source_hash": "2567e0131d51ac69",
+            "traffic_bytes": (120546.5 * 2.0 + 318639.5 * 1.0) * 1024,
+            "hw_fp64_flops": 5804555000.0 * 64}
 
 
 def algorithmic_flops(K, stats, n_rays, method, form):
