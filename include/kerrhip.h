@@ -258,7 +258,9 @@ kh_status kh_init_geodesics(kh_ctx *ctx, int32_t kind, const double *spin, const
  * exactly (bitwise) where it stopped.  Persistent kernel: each 64-lane wave
  * takes rays from a global counter and refills retired lanes, in the order of
  * st->perm if set, else of st->order if set, else of the ray ids; the order
- * changes the run time only, never a result. */
+ * changes the run time only, never a result (for KH_PMIXED with the per-wave
+ * switch, mixed_split = 0, a result can depend on which rays share a wave).
+ * With mixed_split = 1 the call enqueues two such launches (see kh_params). */
 kh_status kh_integrate(kh_ctx *ctx, const kh_params *p, kh_state *st, void *stream);
 
 /* kh_integrate for callers that cannot allocate device memory (code under

@@ -68,6 +68,29 @@ def test_noalloc_equals_integrate_on_two_calls_and_a_resume():
         ctx.close()
 
 
+def test_noalloc_two_queue_mixed_split_equals_integrate():
+    """The two-queue mixed policy enqueues two launches, each clearing the
+    shared counters first: the allocation-free entry point gives bitwise the
+    context entry point's results."""
+    torch.cuda.set_device(0)
+    ctx = K.Context(0)
+    try:
+        p = K.kh_default_params(k_cross=4, precision=K.PMIXED, mixed_split=1)
+        cam = W.kerr_image(17.0, side=64)
+        say("noalloc vs kh_integrate: two-queue mixed split, 64x64")
+        ref = K.State(cam.n, k_cross=4)
+        ctx.kh_init_rays([kcam(cam)], ref)
+        ctx.kh_integrate(p, ref)
+        got = K.State(cam.n, k_cross=4)
+        ctx.kh_init_rays([kcam(cam)], got)
+        K.kh_integrate_noalloc(p, got)
+        torch.cuda.synchronize()
+        assert (got.status == K.CAPTURED).sum() > 100
+        assert_same(ref.numpy(), got.numpy(), "split")
+    finally:
+        ctx.close()
+
+
 def test_noalloc_argument_errors():
     torch.cuda.set_device(0)
     st = K.State(128, k_cross=4)
