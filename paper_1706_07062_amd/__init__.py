@@ -237,14 +237,31 @@ class Context:
         self._check(lib().kh_integrate(self.handle, C.byref(params), C.byref(st.c), _stream(stream)),
                     "kh_integrate")
 
-    def kh_read_state(self, st: "State", first=0, count=None, stream=None):
+    def kh_read_state(self, st: "State", first=0, count=None, stream=None, out=None):
+        """Rows [first, first + count) of the state ([count][8] float64) and
+        their statuses (int32) in host memory.  out: optional (states,
+        statuses) pair of contiguous CPU torch tensors of those shapes and
+        dtypes to fill instead of new numpy arrays; page-locked ones
+        (pin_memory=True) are copied into directly, without the runtime's
+        staging through its own pinned buffers."""
         import numpy as np
 
         count = st.n - first if count is None else count
-        hs = np.zeros((count, 8))
-        hst = np.zeros(count, np.int32)
-        self._check(lib().kh_read_state(self.handle, C.byref(st.c), first, count, hs.ctypes.data,
-                                        hst.ctypes.data, _stream(stream)), "kh_read_state")
+        if out is None:
+            hs = np.zeros((count, 8))
+            hst = np.zeros(count, np.int32)
+            ptrs = (hs.ctypes.data, hst.ctypes.data)
+        else:
+            hs, hst = out
+            if (hs.device.type != "cpu" or hs.dtype != torch.float64 or tuple(hs.shape) != (count, 8)
+                    or not hs.is_contiguous()):
+                raise ValueError("out[0] must be a contiguous CPU float64 tensor of shape (count, 8)")
+            if hst.device.type != "cpu" or hst.dtype != torch.int32 or tuple(hst.shape) != (count,) \
+                    or not hst.is_contiguous():
+                raise ValueError("out[1] must be a contiguous CPU int32 tensor of shape (count,)")
+            ptrs = (hs.data_ptr(), hst.data_ptr())
+        self._check(lib().kh_read_state(self.handle, C.byref(st.c), first, count, ptrs[0], ptrs[1],
+                                        _stream(stream)), "kh_read_state")
         return hs, hst
 
     def kh_stats(self, st: "State", stream=None):

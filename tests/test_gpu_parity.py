@@ -569,6 +569,14 @@ def test_read_state_copies_ranges_to_the_host(ctx):
         hs, hst = ctx.kh_read_state(sb, first, count)
         assert np.array_equal(hs, s[:, first:first + count].T)
         assert np.array_equal(hst, sb.status.cpu().numpy()[first:first + count])
+    # into caller-provided page-locked host tensors (the whole state: two chunks)
+    pinned = (torch.full((big.n, 8), -1.0, dtype=torch.float64, pin_memory=True),
+              torch.full((big.n,), -7, dtype=torch.int32, pin_memory=True))
+    hs, hst = ctx.kh_read_state(sb, 0, big.n, out=pinned)
+    assert hs is pinned[0] and hst is pinned[1]
+    assert np.array_equal(hs.numpy(), s.T) and np.array_equal(hst.numpy(), sb.status.cpu().numpy())
+    with pytest.raises(ValueError):
+        ctx.kh_read_state(sb, 0, 10, out=pinned)
 
 
 def _is_permutation(perm, n):
