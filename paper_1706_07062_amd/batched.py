@@ -83,3 +83,57 @@ class BatchedImages:
     def stats(self) -> dict:
         v = self.stats_dev.cpu().tolist()
         return dict(status_counts=v[:6], n_acc=v[6], n_rej=v[7])
+
+
+class ImageStream:
+    """Frames of images (each a list of cameras with the same total ray count)
+    integrated back to back, with the copy of each frame's final states to
+    host memory overlapping the integration of the next: two device states
+    used in turn, two page-locked host buffers, a compute stream and a copy
+    stream with a context each (a context is not shared between streams that
+    run at the same time).  `consume(frame_index, states, statuses)` gets the
+    host rows ([n][8] float64 and [n] int32 CPU tensors) of each frame in
+    order; they are overwritten two frames later, so it copies what it keeps."""
+
+    def __init__(self, device: int, n: int, params, k_cross: int = 0):
+        self.n = n
+        self.params = params
+        self.cctx = Context(device)
+        self.xctx = Context(device)
+        self.sc = torch.cuda.Stream(device=device)
+        self.sx = torch.cuda.Stream(device=device)
+        self.states = [State(n, k_cross=k_cross, constants=False) for _ in range(2)]
+        self.host = [(torch.empty((n, 8), dtype=torch.float64, pin_memory=True),
+                      torch.empty(n, dtype=torch.int32, pin_memory=True)) for _ in range(2)]
+        self.done = [torch.cuda.Event() for _ in range(2)]
+        torch.cuda.synchronize()
+
+    def run(self, frames, consume):
+        def read(f):
+            b = f % 2
+            self.sx.wait_event(self.done[b])
+            # synchronous on the copy stream: the host rows are complete on return
+            self.xctx.kh_read_state(self.states[b], out=self.host[b], stream=self.sx)
+            consume(f, *self.host[b])
+
+        count = 0
+        for f, cams in enumerate(frames):
+            kc = [camera_struct(c) for c in cams]
+            if sum(c.width * c.height for c in cams) != self.n:
+                raise ValueError(f"frame {f} does not have {self.n} rays")
+            b = f % 2
+            # state b was last read back (synchronously) for frame f - 2
+            self.cctx.kh_init_rays(kc, self.states[b], stream=self.sc)
+            self.cctx.kh_integrate(self.params, self.states[b], stream=self.sc)
+            self.done[b].record(self.sc)
+            if f >= 1:
+                read(f - 1)
+            count = f + 1
+        if count:
+            read(count - 1)
+        torch.cuda.synchronize()
+        return count
+
+    def close(self):
+        self.cctx.close()
+        self.xctx.close()

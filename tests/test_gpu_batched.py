@@ -1,5 +1,6 @@
-"""GPU: many uneven images in one persistent launch, the autotuner, and the
-HIP-graph capture of init -> integrate -> statistics."""
+"""GPU: many uneven images in one persistent launch, the autotuner, the
+HIP-graph capture of init -> integrate -> statistics, and frames streamed
+with the read-back of one overlapping the integration of the next."""
 import json
 
 import numpy as np
@@ -10,7 +11,7 @@ import oracle as O
 import paper_1706_07062_amd as K
 from paper_1706_07062_amd import autotune
 from paper_1706_07062_amd import workloads as W
-from paper_1706_07062_amd.batched import BatchedImages, camera_struct
+from paper_1706_07062_amd.batched import BatchedImages, ImageStream, camera_struct
 from parity_util import oracle_params
 
 pytestmark = pytest.mark.gpu
@@ -192,3 +193,35 @@ def test_batched_full_size_sampled(ctx, tmp_path, monkeypatch):
         f"{np.median(angles):.2e} p99 {np.quantile(angles, 0.99):.2e}")
     assert agree.mean() > 0.99
     assert np.median(angles) < 1e-4
+
+
+def test_image_stream_delivers_every_frame_as_the_sequential_path(ctx):
+    """Five frames of two images (inclination and spin change per frame),
+    integrated with the copy-back of each frame overlapping the next frame's
+    integration on another stream: every frame's host rows and statuses are
+    bitwise those of init, integrate and read-back run one after another."""
+    say("image stream")
+    frames = [[W.Camera(0.9 - 0.1 * f, 1000.0, 20.0 + 12 * f, -12, 12, -12, 12, 64, 64),
+               W.Camera(0.5, 1000.0, 70.0 - 9 * f, -10, 10, -10, 10, 40, 33)] for f in range(5)]
+    n = 64 * 64 + 40 * 33
+    p = K.kh_default_params(k_cross=2)
+    got = {}
+    stream = ImageStream(0, n, p, k_cross=2)
+    try:
+        assert stream.run(frames, lambda f, hs, hst: got.__setitem__(f, (hs.numpy().copy(), hst.numpy().copy()))) == 5
+    finally:
+        stream.close()
+    assert sorted(got) == list(range(5))
+    for f, cams in enumerate(frames):
+        st = K.State(n, k_cross=2, constants=False)
+        ctx.kh_init_rays([camera_struct(c) for c in cams], st)
+        ctx.kh_integrate(p, st)
+        hs, hst = ctx.kh_read_state(st)
+        assert np.array_equal(got[f][0], hs) and np.array_equal(got[f][1], hst), f
+        assert set(np.unique(hst)) <= {K.CAPTURED, K.ESCAPED}
+    bad = ImageStream(0, n + 1, p)
+    try:
+        with pytest.raises(ValueError, match="rays"):
+            bad.run(frames[:1], lambda *a: None)
+    finally:
+        bad.close()
