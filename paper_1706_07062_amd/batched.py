@@ -93,7 +93,10 @@ class ImageStream:
     stream with a context each (a context is not shared between streams that
     run at the same time).  `consume(frame_index, states, statuses)` gets the
     host rows ([n][8] float64 and [n] int32 CPU tensors) of each frame in
-    order; they are overwritten two frames later, so it copies what it keeps."""
+    order; they are overwritten two frames later, so it copies what it keeps.
+    The overlap needs the two streams on different hardware queues; the
+    runtime spreads streams over a few queues (four by default), so create
+    the stream before a program has made many others."""
 
     def __init__(self, device: int, n: int, params, k_cross: int = 0):
         self.n = n
